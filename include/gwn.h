@@ -1,0 +1,233 @@
+/*
+ * gwn.h -- C ABI of the MI355X (gfx950) engine for spatially accelerated
+ * generalized winding numbers (GWN) on curved boundaries.
+ *
+ * The problem (Alg. 1 of the paper, "AgglomeratedGWN"): given a collection of
+ * NURBS objects {Gamma} -- rational Bezier curves in 2D, trimmed rational
+ * bicubic patches in 3D -- and query points {q}, return the GWN w_q at each q
+ * (Eq. gwn_sum: the sum over all primitives of the (solid) angle each one
+ * subtends at q, normalised so that a closed counter-clockwise / outward
+ * oriented boundary gives 1 inside) and the containment decision
+ * inside = (w_q >= 0.5), i.e. round(w_q) >= 1 (Sec. 4.3).
+ *
+ * gwn_build2d / gwn_build3d run the preprocessing phase of Alg. 1 on the host
+ * (adaptive subdivision to the 10% bounding-box rule of Sec. 3.2, uncentered
+ * moments of Sec. 3.1, Karras BVH, moment up-sweep and centering) and upload
+ * the result to one GPU.  gwn_query runs the query phase of Alg. 1 on the
+ * GPU: BVH traversal, the far-field test ||q - centroid|| > beta * radius,
+ * the order-0..2 Taylor approximation of Eq. taylor for far clusters, and
+ * direct evaluation (Sec. 3.3) of every leaf reached.
+ *
+ * Conventions common to every entry point:
+ *  - Every function returns a gwn_status; GWN_OK is 0.  On any other status
+ *    gwn_last_error() returns a message (thread-local, valid until the next
+ *    call on the same thread).  No C++ exception crosses this boundary.
+ *  - Host arrays passed to gwn_build* are read during the call only and are
+ *    never retained: the caller keeps ownership.
+ *  - Query points and outputs are DEVICE pointers owned by the caller.  Query
+ *    calls only enqueue work on `stream` (a hipStream_t, NULL = the null
+ *    stream) and return without synchronising; results are ready when the
+ *    stream reaches that point.  Scratch memory is taken from HIP's
+ *    stream-ordered allocator and released on the same stream.
+ *  - A handle is immutable while queries may be in flight, and may be queried
+ *    from several streams at once.  gwn_set_params and gwn_free must not race
+ *    with queries that use the handle.
+ */
+#ifndef GWN_H
+#define GWN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gwn_model *gwn_handle;
+typedef int32_t gwn_status;
+
+enum {
+    GWN_OK = 0,
+    GWN_EINVAL = 1,        /* invalid argument or malformed geometry            */
+    GWN_ENOMEM = 2,        /* host or device allocation failed                  */
+    GWN_EHIP = 3,          /* a HIP runtime call failed (message has the code)  */
+    GWN_EUNSUPPORTED = 4,  /* valid request the engine does not implement       */
+    GWN_EOVERFLOW = 5      /* a traversal or subdivision stack limit was hit    */
+};
+
+enum { GWN_FP64 = 0, GWN_MIXED = 1 };
+
+/* 2D input: rational Bezier curves of degree 1..3 (Sec. 3, P0 of Alg. 1).
+ * Curve i has control points cp_xy[2*k], cp_xy[2*k+1] and weights cp_w[k]
+ * for k in [cp_offset[i], cp_offset[i+1]), which must hold degree[i]+1
+ * points.  Weights must be finite and > 0, coordinates finite. */
+typedef struct {
+    int64_t n_curves;
+    const int32_t *degree;     /* [n_curves]                  */
+    const int64_t *cp_offset;  /* [n_curves + 1], cp_offset[0] == 0 */
+    const double *cp_xy;       /* [2 * n_cp] Euclidean points */
+    const double *cp_w;        /* [n_cp] weights              */
+} gwn_curves2d;
+
+/* 3D input: rational bicubic Bezier patches with optional trimming (Sec. 3.1,
+ * Fig. quadrature_demo).  Patch i has control points
+ * cp_xyz[48*i + 3*(4*a + b) + axis] (a indexes u, b indexes v) and weights
+ * cp_w[16*i + 4*a + b] (> 0).  Its trim curves are trim_offset[i] ..
+ * trim_offset[i+1]-1 (an empty range means the whole square [0,1]^2 is
+ * visible).  Trim curve c is a rational Bezier in (u, v) of degree
+ * trim_degree[c] (1 or 2) with control points trim_cp_uv[2*k..2*k+1] and
+ * weights trim_cp_w[k] for k in [trim_cp_offset[c], trim_cp_offset[c+1]).
+ * A patch's trim curves form closed loops of consecutive curves inside
+ * [0,1]^2: the outer boundary counter-clockwise (the square must be given
+ * explicitly when other loops are present), holes clockwise.  The surface
+ * normal S_u x S_v must point out of the body. */
+typedef struct {
+    int64_t n_patches;
+    const double *cp_xyz;          /* [48 * n_patches] */
+    const double *cp_w;            /* [16 * n_patches] */
+    const int64_t *trim_offset;    /* [n_patches + 1]  */
+    const int32_t *trim_degree;    /* [n_trim]         */
+    const int64_t *trim_cp_offset; /* [n_trim + 1]     */
+    const double *trim_cp_uv;      /* [2 * n_trim_cp]  */
+    const double *trim_cp_w;       /* [n_trim_cp]      */
+} gwn_patches3d;
+
+/* Parameters.  Build-time fields fix the tree; query-time fields (marked Q)
+ * may be changed later with gwn_set_params. */
+typedef struct {
+    double beta;           /* Q: far-field factor of the FP64 form: a cluster is
+                              far when ||q - c|| > beta * r, r = AABB half
+                              diagonal (Alg. 1; default 2, Sec. 3).  2D needs
+                              beta >= 2 (chord substitution, Sec. 3.1).       */
+    double beta_mixed;     /* Q: far-field factor of the FP32 pass of the mixed
+                              form (default 4)                               */
+    int32_t taylor_order;  /* Q: expansion order of Eq. taylor; default 2
+                              (Sec. 4.2).  3D: 0..2.  2D: 0..8 -- orders above
+                              2 carry the same expansion further (exact chord
+                              moments, complex form)                          */
+    int32_t precision;     /* Q: GWN_FP64 or GWN_MIXED                         */
+    double reclass_band;   /* Q: mixed form: queries with |w - 0.5| < band are
+                              re-evaluated in FP64 (default 1e-2)            */
+    double max_diag_frac;  /* subdivision threshold: split a primitive while its
+                              AABB diagonal >= frac * model diagonal
+                              (default 0.10, Sec. 3.2)                        */
+    double eps_on;         /* on-boundary distance relative to the model
+                              diagonal (default 1e-12)                        */
+    int32_t gl_nodes;      /* 3D: Gauss-Legendre nodes per rule for leaf and
+                              moment quadrature (default 10, Sec. 3.1)        */
+    int32_t device;        /* HIP device ordinal; -1 builds a host-only handle
+                              that can be inspected but not queried           */
+    double near_ratio;     /* Q, 3D: a leaf is evaluated with the adaptive
+                              near-field rule when dist(q, AABB) <
+                              near_ratio * AABB diagonal (default 0.5)        */
+    double eps_q;          /* Q, 3D: near-field quadrature tolerance per leaf
+                              (default 1e-10)                                 */
+} gwn_params;
+
+/* Fill *p with the defaults listed above. */
+void gwn_default_params(gwn_params *p);
+
+/* Build a 2D model (Alg. 1 preprocessing).  `curves` and `params` are read
+ * during the call only.  On success *out owns host and device memory until
+ * gwn_free.  Errors: GWN_EINVAL (NULL pointers, bad degree/offsets/weights,
+ * non-finite data, beta < 2), GWN_ENOMEM, GWN_EHIP, GWN_EOVERFLOW (tree deeper
+ * than the traversal stack). */
+gwn_status gwn_build2d(const gwn_curves2d *curves, const gwn_params *params, gwn_handle *out);
+
+/* Build a 3D model (Alg. 1 preprocessing, moments by Gauss-Legendre quadrature
+ * over the trimmed domain via Green's theorem, Sec. 3.1).  Errors as for
+ * gwn_build2d, plus GWN_EINVAL for trim curves outside [0,1]^2, open trim
+ * loops or a bad trim degree. */
+gwn_status gwn_build3d(const gwn_patches3d *patches, const gwn_params *params, gwn_handle *out);
+
+/* Replace the query-time (Q) fields of a handle's parameters.  Build-time
+ * fields of `params` are ignored.  GWN_EINVAL for out-of-range values. */
+gwn_status gwn_set_params(gwn_handle h, const gwn_params *params);
+
+/* Read back a handle's parameters. */
+gwn_status gwn_get_params(gwn_handle h, gwn_params *out);
+
+/* Query phase of Alg. 1.  points: device double[n * dim] interleaved
+ * (x, y[, z]); out_gwn: device double[n]; out_inside: device uint8[n]
+ * (1 when w >= 0.5) or NULL.  n may be 0.  Asynchronous on `stream`.
+ * Errors: GWN_EINVAL (NULL handle, n < 0, NULL buffers with n > 0, host-only
+ * handle), GWN_EHIP, GWN_EOVERFLOW (reported by the NEXT call on the handle
+ * after a kernel hit a stack limit; the affected outputs are NaN). */
+gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
+                     uint8_t *out_inside, void *stream);
+
+/* Batched query over several models in shared launches (the served form).
+ * Segment s covers query rows [seg_offset[s], seg_offset[s+1]) of `points`,
+ * `out_gwn` and `out_inside` and is evaluated against model seg_model[s].
+ * seg_model and seg_offset are HOST arrays (n_seg and n_seg + 1 entries,
+ * seg_offset[0] == 0, non-decreasing); points/outputs are device arrays whose
+ * row width follows each segment's model dimension: 2D and 3D segments may
+ * not share one call (GWN_EINVAL).  Every row's result is bitwise identical
+ * to what gwn_query returns for that row alone. */
+gwn_status gwn_query_batch(int32_t n_seg, const gwn_handle *seg_model, const int64_t *seg_offset,
+                           const double *points, double *out_gwn, uint8_t *out_inside,
+                           void *stream);
+
+/* Work counters of one query pass (same traversal, instrumented), summed over
+ * all n queries into the device array counters[GWN_NCOUNTERS] (int64,
+ * overwritten).  Used to compute algorithmic work.  Order of entries: */
+enum {
+    GWN_C_NODES = 0,       /* internal nodes tested                        */
+    GWN_C_FAR = 1,         /* clusters evaluated by the Taylor expansion   */
+    GWN_C_LEAVES = 2,      /* leaves evaluated directly                    */
+    GWN_C_LEAF_FAST = 3,   /* 2D: leaves resolved by one chord angle;
+                              3D: leaves evaluated by the precomputed rule */
+    GWN_C_PIECES = 4,      /* 2D: bisection pieces examined near q;
+                              3D: near-field integrand evaluations         */
+    GWN_C_ANGLES = 5,      /* 2D: atan2 evaluations; 3D: far-rule nodes    */
+    GWN_C_RECLASS = 6,     /* mixed form: queries re-evaluated in FP64     */
+    GWN_C_OVERFLOW = 7,    /* queries that hit a stack limit               */
+    GWN_NCOUNTERS = 8
+};
+gwn_status gwn_query_counters(gwn_handle h, const double *points, int64_t n, int64_t *counters,
+                              void *stream);
+
+/* Memory accounting: bytes resident on the device for this model, and device
+ * scratch bytes needed per query by gwn_query / gwn_query_batch. */
+gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_scratch);
+
+/* Host-side inspection of a built model (also for host-only handles).  Copies
+ * up to `capacity` items of kind `what` into `out` and stores the total item
+ * count in *count.  Kinds and item layouts (all double unless noted):
+ *   GWN_I_SUMMARY   1 item of 8 doubles: dim, n_input, n_leaves, n_nodes,
+ *                   tree depth, model diagonal, bbox_lo[0], bbox_hi[0]
+ *   GWN_I_LEAVES    per leaf (in BVH leaf order): input primitive index, then
+ *                   the leaf's homogeneous control points (2D: 4 x (wx,wy,w);
+ *                   3D: 16 x (wx,wy,wz,w)) -- 13 or 65 doubles
+ *   GWN_I_NODES     per node (DFS order): is_leaf, left, right, centroid[3],
+ *                   r (AABB half diagonal), aabb_lo[3], aabb_hi[3]  -- 13 doubles
+ *   GWN_I_MOMENTS   per node: centred Cartesian moments (Eq. taylor) about the
+ *                   centroid, M0[d], M1[d*d] (M1[j*d+k] = int (x-c)_j n_k),
+ *                   M2[d*d*d] (M2[(i*d+j)*d+k] = int (x-c)_i (x-c)_j n_k);
+ *                   14 doubles in 2D, 39 in 3D
+ *   GWN_I_UNCENTERED per node: the uncentered moments (same layout)
+ *   GWN_I_COMPLEX   2D only, per node: the centred complex moments
+ *                   m_k = integral over the cluster's chords of (z - c)^k dz,
+ *                   k = 0..8, as (re, im) pairs -- 18 doubles (zero for leaves)
+ */
+enum { GWN_I_SUMMARY = 0, GWN_I_LEAVES = 1, GWN_I_NODES = 2, GWN_I_MOMENTS = 3, GWN_I_UNCENTERED = 4,
+       GWN_I_COMPLEX = 5 };
+gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64_t capacity, int64_t *count);
+
+/* Kernel timing.  gwn_profile(1, NULL, NULL) starts recording a pair of HIP
+ * events around every traversal-kernel launch (on the stream the kernel runs
+ * on); gwn_profile(0, &ms, &launches) waits for the recorded events, returns
+ * the summed traversal-kernel time in milliseconds and the number of
+ * launches, and stops recording.  Process-wide; not for concurrent use. */
+gwn_status gwn_profile(int32_t enable, double *total_ms, int64_t *launches);
+
+/* Release a handle (host and device memory).  NULL is accepted. */
+gwn_status gwn_free(gwn_handle h);
+
+/* Message for the last non-OK status on this thread. */
+const char *gwn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWN_H */

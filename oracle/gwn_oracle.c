@@ -143,13 +143,17 @@ static int cmp_dbl(const void *x, const void *y)
 }
 
 #define MAX_BREAKS 1024
+#define UNIFORM_2D 64   /* initial uniform panels, 2D angle integral */
+#define UNIFORM_3D 2    /* initial uniform panels, each 3D level */
 static double graded(fn1 f, void *ctx, double a, double b, const double *centres,
-                     const double *h0, int nc, double tol)
+                     const double *h0, int nc, double tol, int uniform)
 {
     double br[MAX_BREAKS];
     int nb = 0;
-    br[nb++] = a;
-    br[nb++] = b;
+    /* a uniform partition first, so that features away from the centres
+     * (e.g. fast parameter speed at a sharp turn) are seen by the error
+     * estimate; then the graded breakpoints */
+    for (int i = 0; i <= uniform; ++i) br[nb++] = a + (b - a) * i / uniform;
     for (int k = 0; k < nc; ++k) {
         double c = centres[k], h = h0[k];
         if (!(h > 0.0)) continue;
@@ -351,7 +355,7 @@ static double gwn_curve(const curve2 *c, double eps_on)
     if (d < eps_on && speed > 0.0) return gwn_curve_onboundary(c, sx, sy, eps_on);
     double h0 = fmax(d, eps_on) / speed;
     if (!(h0 > 0.0)) h0 = 1e-16;
-    return graded(dtheta, (void *)c, 0.0, 1.0, &ts, &h0, 1, 1e-14);
+    return graded(dtheta, (void *)c, 0.0, 1.0, &ts, &h0, 1, 1e-14, UNIFORM_2D);
 }
 
 /*
@@ -532,7 +536,7 @@ static double F_inner(green_ctx *g, double u, double v)
     double dx = S[0] - g->p->q[0], dy = S[1] - g->p->q[1], dz = S[2] - g->p->q[2];
     double dist = sqrt(dx * dx + dy * dy + dz * dz);
     double h0 = fmax(dist, g->eps_on) / (g->su + 1e-300);
-    return graded(inner_g, g, 0.0, u, &c, &h0, 1, 1e-15);
+    return graded(inner_g, g, 0.0, u, &c, &h0, 1, 1e-15, UNIFORM_3D);
 }
 
 static void trim_eval(const green_ctx *g, double t, double *u, double *v, double *du, double *dv)
@@ -600,7 +604,7 @@ static double trim_contribution(green_ctx *g)
         double speed = g->su * fabs(du) + g->sv * fabs(dv);
         h0[k] = fmax(dist, g->eps_on) / (speed + 1e-300);
     }
-    return graded(outer_f, g, 0.0, 1.0, centres, h0, nc, 1e-14);
+    return graded(outer_f, g, 0.0, 1.0, centres, h0, nc, 1e-14, UNIFORM_3D);
 }
 
 static double gwn_patch(const patch3 *p, int n_trim, const int32_t *tdeg, const int64_t *tcoff,

@@ -1,0 +1,250 @@
+// Host preprocessing of a 2D model (Alg. 1, threaded preprocessing):
+//   AdaptiveSubdivision -> ComputeUncenteredMoments -> ConstructBVH ->
+//   SumUncenteredMomentsUpTree -> CenterMomentsInPlace.
+//
+// Curves of degree 1..3 are degree-elevated to cubics (exact) so the kernels
+// handle one shape of record; the original degree is kept for the straight
+// segment fast path.
+//
+// Moments use the chord substitution of Sec. 3.1: far from a curve, the curve
+// subtends the same angle as the segment joining its end points (the closed
+// loop curve + reversed chord lies in the control polygon's convex hull, hence
+// in its AABB, and the far test with beta >= 2 keeps q outside every AABB of an
+// accepted cluster).  The uncentered moments of a segment a -> b with
+// d = b - a and normal measure n ds = N ds, N = (d_y, -d_x) (outward for a
+// counter-clockwise loop) are exact:
+//   int n      = N
+//   int x (x) n = (a + d/2) (x) N
+//   int x (x) x (x) n = (a a^T + (a d^T + d a^T)/2 + d d^T / 3) (x) N
+// and the centroid weight is the chord length with its midpoint.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "gwn_internal.h"
+
+namespace gwn {
+
+namespace {
+
+struct Cubic {
+    double h[12];  // (wx, wy, w) x 4
+    int degree;
+    int64_t src;
+};
+
+void elevate_to_cubic(const double *xy, const double *w, int deg, double *h)
+{
+    double p[4][3];
+    for (int i = 0; i <= deg; ++i) {
+        p[i][0] = xy[2 * i] * w[i];
+        p[i][1] = xy[2 * i + 1] * w[i];
+        p[i][2] = w[i];
+    }
+    int n = deg;
+    while (n < 3) {
+        double q[4][3];
+        for (int k = 0; k < 3; ++k) {
+            q[0][k] = p[0][k];
+            q[n + 1][k] = p[n][k];
+        }
+        for (int i = 1; i <= n; ++i) {
+            double a = (double)i / (n + 1);
+            for (int k = 0; k < 3; ++k) q[i][k] = a * p[i - 1][k] + (1.0 - a) * p[i][k];
+        }
+        ++n;
+        std::memcpy(p, q, sizeof p);
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 3; ++k) h[3 * i + k] = p[i][k];
+}
+
+void split_half(const double *h, double *L, double *R)
+{
+    // de Casteljau at t = 1/2 in homogeneous coordinates
+    double a[4][3];
+    for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 3; ++k) a[i][k] = h[3 * i + k];
+    for (int k = 0; k < 3; ++k) {
+        double b0 = 0.5 * (a[0][k] + a[1][k]), b1 = 0.5 * (a[1][k] + a[2][k]), b2 = 0.5 * (a[2][k] + a[3][k]);
+        double c0 = 0.5 * (b0 + b1), c1 = 0.5 * (b1 + b2);
+        double d0 = 0.5 * (c0 + c1);
+        L[k] = a[0][k]; L[3 + k] = b0; L[6 + k] = c0; L[9 + k] = d0;
+        R[k] = d0; R[3 + k] = c1; R[6 + k] = b2; R[9 + k] = a[3][k];
+    }
+}
+
+void aabb(const double *h, double *lo, double *hi)
+{
+    lo[0] = lo[1] = INFINITY;
+    hi[0] = hi[1] = -INFINITY;
+    lo[2] = hi[2] = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        double x = h[3 * i] / h[3 * i + 2], y = h[3 * i + 1] / h[3 * i + 2];
+        lo[0] = std::min(lo[0], x); hi[0] = std::max(hi[0], x);
+        lo[1] = std::min(lo[1], y); hi[1] = std::max(hi[1], y);
+    }
+}
+
+}  // namespace
+
+gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, std::string &err)
+{
+    const int64_t n = c->n_curves;
+    if (n < 0) { err = "n_curves < 0"; return GWN_EINVAL; }
+    if (n > 0 && (!c->degree || !c->cp_offset || !c->cp_xy || !c->cp_w)) {
+        err = "NULL curve array";
+        return GWN_EINVAL;
+    }
+    if (n > (int64_t)1 << 28) { err = "too many curves"; return GWN_EINVAL; }
+    if (n > 0 && c->cp_offset[0] != 0) { err = "cp_offset[0] must be 0"; return GWN_EINVAL; }
+    m.dim = 2;
+    m.params = *p;
+    m.n_input = n;
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+    std::vector<Cubic> work;
+    work.reserve((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int d = c->degree[i];
+        if (d < 1 || d > 3) { err = "curve " + std::to_string(i) + ": degree must be 1..3"; return GWN_EINVAL; }
+        int64_t a = c->cp_offset[i], b = c->cp_offset[i + 1];
+        if (b - a != d + 1) { err = "curve " + std::to_string(i) + ": cp_offset does not match degree"; return GWN_EINVAL; }
+        for (int64_t k = a; k < b; ++k) {
+            double x = c->cp_xy[2 * k], y = c->cp_xy[2 * k + 1], w = c->cp_w[k];
+            if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(w)) {
+                err = "curve " + std::to_string(i) + ": non-finite control data";
+                return GWN_EINVAL;
+            }
+            if (!(w > 0.0)) { err = "curve " + std::to_string(i) + ": weights must be > 0"; return GWN_EINVAL; }
+            lo[0] = std::min(lo[0], x); hi[0] = std::max(hi[0], x);
+            lo[1] = std::min(lo[1], y); hi[1] = std::max(hi[1], y);
+        }
+        Cubic cu;
+        elevate_to_cubic(c->cp_xy + 2 * a, c->cp_w + a, d, cu.h);
+        cu.degree = d;
+        cu.src = i;
+        work.push_back(cu);
+    }
+    if (n == 0) { lo[0] = lo[1] = 0; hi[0] = hi[1] = 0; }
+    m.lo[0] = lo[0]; m.lo[1] = lo[1]; m.hi[0] = hi[0]; m.hi[1] = hi[1];
+    m.lo[2] = m.hi[2] = 0;
+    m.diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]));
+
+    // AdaptiveSubdivision (Sec. 3.2): bisect while the AABB diagonal is not
+    // below max_diag_frac of the model diagonal.  Depth is capped at 40.
+    const double limit = p->max_diag_frac * m.diag;
+    std::vector<Cubic> leaves;
+    leaves.reserve(work.size());
+    struct Item { Cubic c; int depth; };
+    std::vector<Item> st;
+    for (int64_t i = (int64_t)work.size() - 1; i >= 0; --i) st.push_back({work[i], 0});
+    while (!st.empty()) {
+        Item it = st.back();
+        st.pop_back();
+        double l[3], h[3];
+        aabb(it.c.h, l, h);
+        double dg = std::hypot(h[0] - l[0], h[1] - l[1]);
+        if (limit > 0 && dg >= limit && it.depth < 40) {
+            Cubic L = it.c, R = it.c;
+            split_half(it.c.h, L.h, R.h);
+            st.push_back({R, it.depth + 1});
+            st.push_back({L, it.depth + 1});
+        } else {
+            leaves.push_back(it.c);
+        }
+    }
+    const int nl = (int)leaves.size();
+    if ((int64_t)nl > ((int64_t)1 << 30)) { err = "too many leaves"; return GWN_EINVAL; }
+
+    // ComputeUncenteredMoments: exact chord moments per leaf.
+    const int nm = n_moments(2);
+    std::vector<double> LO(3 * (size_t)nl), HI(3 * (size_t)nl), U((size_t)nl * nm), Wt(nl), WC(3 * (size_t)nl);
+    for (int i = 0; i < nl; ++i) {
+        const double *h = leaves[i].h;
+        aabb(h, &LO[3 * i], &HI[3 * i]);
+        double ax = h[0] / h[2], ay = h[1] / h[2], bx = h[9] / h[11], by = h[10] / h[11];
+        double dx = bx - ax, dy = by - ay;
+        double N[2] = {dy, -dx};
+        double A[2] = {ax, ay}, D[2] = {dx, dy};
+        double *u = &U[(size_t)i * nm];
+        u[0] = N[0];
+        u[1] = N[1];
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) u[2 + 2 * j + k] = (A[j] + 0.5 * D[j]) * N[k];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                double s = A[a] * A[b] + 0.5 * (A[a] * D[b] + D[a] * A[b]) + D[a] * D[b] / 3.0;
+                for (int k = 0; k < 2; ++k) u[6 + (2 * a + b) * 2 + k] = s * N[k];
+            }
+        double len = std::hypot(dx, dy);
+        Wt[i] = len;
+        WC[3 * i] = len * 0.5 * (ax + bx);
+        WC[3 * i + 1] = len * 0.5 * (ay + by);
+        WC[3 * i + 2] = 0;
+    }
+    if (!build_tree(2, nl, LO.data(), HI.data(), U.data(), Wt.data(), WC.data(), m.lo, m.hi, m.tree, err))
+        return GWN_EINVAL;
+    if (m.tree.depth > kStackDepth) {
+        err = "BVH depth " + std::to_string(m.tree.depth) + " exceeds the traversal stack";
+        return GWN_EOVERFLOW;
+    }
+    // Complex moments about each node's own centroid, summed directly over
+    // the chords of its subtree: m_k = sum (b-c)^{k+1} - (a-c)^{k+1} / (k+1),
+    // written as (b - a) sum_j (b-c)^j (a-c)^{k-j} / (k+1) to avoid the
+    // cancellation of short chords.  (Summing uncentered moments and shifting
+    // them, as done for the Cartesian order-2 moments, loses about
+    // k log10(|c| / r) digits at order k.)  A DFS subtree is the contiguous
+    // node range [i, end_i).
+    {
+        const int nn = (int)m.tree.nodes.size();
+        const int K = kMaxOrder2D + 1;
+        std::vector<int> end(nn);
+        for (int i = nn - 1; i >= 0; --i) {
+            const HostNode &nd = m.tree.nodes[i];
+            end[i] = nd.is_leaf ? i + 1 : end[nd.right];
+        }
+        m.cmom2.assign((size_t)nn * 2 * K, 0.0);
+        for (int i = 0; i < nn; ++i) {
+            const HostNode &nd = m.tree.nodes[i];
+            if (nd.is_leaf) continue;
+            double *out = &m.cmom2[(size_t)i * 2 * K];
+            for (int j = i; j < end[i]; ++j) {
+                const HostNode &lf = m.tree.nodes[j];
+                if (!lf.is_leaf) continue;
+                const double *hh = leaves[lf.leaf].h;
+                double ar = hh[0] / hh[2] - nd.c[0], ai = hh[1] / hh[2] - nd.c[1];
+                double br = hh[9] / hh[11] - nd.c[0], bi = hh[10] / hh[11] - nd.c[1];
+                double dr = br - ar, di = bi - ai;
+                // s_k = sum_{j<=k} b^j a^{k-j}: s_0 = 1, s_k = b s_{k-1} + a^k
+                double sr = 1.0, si = 0.0, pr = 1.0, pi = 0.0;  // p = a^k
+                for (int k = 0; k < K; ++k) {
+                    if (k > 0) {
+                        double npr = pr * ar - pi * ai, npi = pr * ai + pi * ar;
+                        pr = npr; pi = npi;
+                        double nsr = br * sr - bi * si + pr, nsi = br * si + bi * sr + pi;
+                        sr = nsr; si = nsi;
+                    }
+                    out[2 * k] += (dr * sr - di * si) / (k + 1);
+                    out[2 * k + 1] += (dr * si + di * sr) / (k + 1);
+                }
+            }
+        }
+    }
+    // leaves in BVH leaf order (order of appearance in the DFS layout)
+    m.leaf_src.clear();
+    m.leaf_h.clear();
+    m.leaf_degree.clear();
+    std::vector<int> leaf_pos(nl, -1);
+    for (auto &nd : m.tree.nodes)
+        if (nd.is_leaf) {
+            int src = nd.leaf;
+            nd.leaf = (int)m.leaf_src.size();
+            leaf_pos[src] = nd.leaf;
+            m.leaf_src.push_back(leaves[src].src);
+            m.leaf_h.insert(m.leaf_h.end(), leaves[src].h, leaves[src].h + 12);
+            m.leaf_degree.push_back(leaves[src].degree);
+        }
+    return GWN_OK;
+}
+
+}  // namespace gwn

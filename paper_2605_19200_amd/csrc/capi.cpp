@@ -1,0 +1,496 @@
+// C ABI of the engine (declared in include/gwn.h): validation, parameter
+// handling, packing of the host tree into device records and upload.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gwn_internal.h"
+
+using namespace gwn;
+
+static thread_local std::string g_err;
+
+static gwn_status fail(gwn_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+static gwn_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(GWN_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct gwn_model {
+    Model m;
+};
+
+extern "C" void gwn_default_params(gwn_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->beta = 2.0;
+    p->beta_mixed = 4.0;
+    p->taylor_order = 2;
+    p->precision = GWN_FP64;
+    p->reclass_band = 1e-2;
+    p->max_diag_frac = 0.10;
+    p->eps_on = 1e-12;
+    p->gl_nodes = 10;
+    p->device = 0;
+    p->near_ratio = 0.5;
+    p->eps_q = 1e-10;
+}
+
+static gwn_status check_query_params(int dim, const gwn_params *p)
+{
+    if (!(p->beta > 0) || !std::isfinite(p->beta)) return fail(GWN_EINVAL, "beta must be finite and > 0");
+    if (!(p->beta_mixed > 0) || !std::isfinite(p->beta_mixed))
+        return fail(GWN_EINVAL, "beta_mixed must be finite and > 0");
+    if (dim == 2 && (p->beta < 2.0 || p->beta_mixed < 2.0))
+        return fail(GWN_EINVAL, "2D requires beta >= 2 (chord substitution needs q outside every accepted AABB)");
+    if (p->taylor_order < 0 || p->taylor_order > (dim == 2 ? kMaxOrder2D : 2))
+        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..8 in 2D" : "taylor_order must be 0, 1 or 2 in 3D");
+    if (p->precision != GWN_FP64 && p->precision != GWN_MIXED) return fail(GWN_EINVAL, "bad precision");
+    if (!(p->reclass_band >= 0) || !std::isfinite(p->reclass_band)) return fail(GWN_EINVAL, "bad reclass_band");
+    if (!(p->near_ratio >= 0) || !std::isfinite(p->near_ratio)) return fail(GWN_EINVAL, "bad near_ratio");
+    if (!(p->eps_q > 0)) return fail(GWN_EINVAL, "eps_q must be > 0");
+    return GWN_OK;
+}
+
+static gwn_status check_build_params(int dim, const gwn_params *p)
+{
+    gwn_status s = check_query_params(dim, p);
+    if (s) return s;
+    if (!(p->max_diag_frac >= 0) || !std::isfinite(p->max_diag_frac)) return fail(GWN_EINVAL, "bad max_diag_frac");
+    if (!(p->eps_on >= 0) || !std::isfinite(p->eps_on)) return fail(GWN_EINVAL, "bad eps_on");
+    if (p->gl_nodes < 1 || p->gl_nodes > 32) return fail(GWN_EINVAL, "gl_nodes must be 1..32");
+    return GWN_OK;
+}
+
+namespace gwn {
+
+void refresh_dev_params(Model &m)
+{
+    const gwn_params &p = m.params;
+    m.dev.dim = m.dim;
+    m.dev.order = p.taylor_order;
+    m.dev.precision = p.precision;
+    m.dev.beta2 = p.beta * p.beta;
+    m.dev.beta2_mixed = p.beta_mixed * p.beta_mixed;
+    m.dev.band = p.reclass_band;
+    for (int a = 0; a < 3; ++a) {
+        m.dev.lo[a] = m.lo[a];
+        double ext = m.hi[a] - m.lo[a];
+        m.dev.inv_ext[a] = ext > 0 ? 1.0 / ext : 0.0;
+    }
+    m.dev.eps_on = p.eps_on * m.diag;
+    m.dev.near_ratio2 = p.near_ratio * p.near_ratio;
+    m.dev.eps_q = p.eps_q;
+    m.dev.gl_n = p.gl_nodes;
+}
+
+static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Prim2> &prims)
+{
+    const auto &T = m.tree.nodes;
+    nodes.assign(T.size(), Node2{});
+    for (size_t i = 0; i < T.size(); ++i) {
+        const HostNode &h = T[i];
+        Node2 &n = nodes[i];
+        std::memset(&n, 0, sizeof n);
+        n.c[0] = h.c[0];
+        n.c[1] = h.c[1];
+        n.r2 = h.r * h.r;
+        if (h.is_leaf) {
+            n.m[0] = h.lo[0]; n.m[1] = h.lo[1]; n.m[2] = h.hi[0]; n.m[3] = h.hi[1];
+            n.right = -1 - h.leaf;
+            n.degree = m.leaf_degree[h.leaf];
+        } else {
+            // centred complex moments m_k = integral (z - c)^k dz (build2d)
+            std::memcpy(n.m, &m.cmom2[i * 2 * (kMaxOrder2D + 1)], sizeof(n.m));
+            n.right = h.right;
+            n.degree = 0;
+        }
+        n.fc[0] = (float)n.c[0];
+        n.fc[1] = (float)n.c[1];
+        n.fr2 = (float)n.r2;
+        for (int k = 0; k < 2 * kMaxOrder2D; ++k) n.fm[k] = (float)n.m[k];
+    }
+    prims.assign(m.leaf_src.size(), Prim2{});
+    for (size_t l = 0; l < prims.size(); ++l)
+        std::memcpy(prims[l].h, &m.leaf_h[12 * l], sizeof(double) * 12);
+}
+
+void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims);  // build3d.cpp
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+gwn_status upload_model(Model &m, std::string &err)
+{
+    hipError_t e = hipSetDevice(m.device);
+    if (e != hipSuccess) { err = std::string("hipSetDevice: ") + hipGetErrorString(e); return GWN_EHIP; }
+    // Arena: nodes | prims | trims | qnodes, each 256-byte aligned.
+    std::vector<Node2> n2; std::vector<Prim2> p2;
+    std::vector<Node3> n3; std::vector<Prim3> p3;
+    const void *src[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t bytes[4] = {0, 0, 0, 0};
+    if (m.dim == 2) {
+        pack2d(m, n2, p2);
+        src[0] = n2.data(); bytes[0] = n2.size() * sizeof(Node2);
+        src[1] = p2.data(); bytes[1] = p2.size() * sizeof(Prim2);
+    } else {
+        pack3d(m, n3, p3);
+        src[0] = n3.data(); bytes[0] = n3.size() * sizeof(Node3);
+        src[1] = p3.data(); bytes[1] = p3.size() * sizeof(Prim3);
+        src[2] = m.trims.data(); bytes[2] = m.trims.size() * sizeof(Trim3);
+        src[3] = m.qnodes.data(); bytes[3] = m.qnodes.size() * sizeof(QNode3);
+    }
+    size_t off[5];
+    off[0] = 0;
+    for (int k = 0; k < 4; ++k) off[k + 1] = align_up(off[k] + bytes[k], 256);
+    size_t total = std::max<size_t>(off[4], 256);
+    void *arena = nullptr;
+    e = hipMalloc(&arena, total);
+    if (e != hipSuccess) { err = std::string("hipMalloc arena: ") + hipGetErrorString(e); return GWN_ENOMEM; }
+    for (int k = 0; k < 4; ++k)
+        if (bytes[k]) {
+            e = hipMemcpy((char *)arena + off[k], src[k], bytes[k], hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(arena);
+                err = std::string("hipMemcpy arena: ") + hipGetErrorString(e);
+                return GWN_EHIP;
+            }
+        }
+    int32_t *flag = nullptr;
+    e = hipMalloc((void **)&flag, 256);
+    if (e == hipSuccess) e = hipMemset(flag, 0, 256);
+    int32_t *hflag = nullptr;
+    if (e == hipSuccess) e = hipHostMalloc((void **)&hflag, 256, hipHostMallocDefault);
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipFree(arena);
+        if (flag) (void)hipFree(flag);
+        if (hflag) (void)hipHostFree(hflag);
+        err = std::string("device flag setup: ") + hipGetErrorString(e);
+        return GWN_EHIP;
+    }
+    *hflag = 0;
+    m.d_arena = arena;
+    m.arena_bytes = (int64_t)total;
+    m.d_flag = flag;
+    m.h_flag = hflag;
+    m.flag_event = ev;
+    m.dev.nodes = (char *)arena + off[0];
+    m.dev.prims = (char *)arena + off[1];
+    m.dev.trims = (char *)arena + off[2];
+    m.dev.qnodes = (char *)arena + off[3];
+    m.dev.flag = flag;
+    m.dev.n_nodes = (int32_t)m.tree.nodes.size();
+    refresh_dev_params(m);
+    return GWN_OK;
+}
+
+void release_device(Model &m)
+{
+    if (m.device < 0) return;
+    (void)hipSetDevice(m.device);
+    if (m.flag_event) (void)hipEventSynchronize((hipEvent_t)m.flag_event);
+    (void)hipDeviceSynchronize();
+    if (m.d_arena) (void)hipFree(m.d_arena);
+    if (m.d_flag) (void)hipFree(m.d_flag);
+    if (m.h_flag) (void)hipHostFree(m.h_flag);
+    if (m.flag_event) (void)hipEventDestroy((hipEvent_t)m.flag_event);
+    m.d_arena = nullptr;
+    m.d_flag = nullptr;
+    m.h_flag = nullptr;
+    m.flag_event = nullptr;
+}
+
+}  // namespace gwn
+
+template <class F>
+static gwn_status build_common(int dim, const gwn_params *params, gwn_handle *out, F &&host_build)
+{
+    if (!out) return fail(GWN_EINVAL, "out handle pointer is NULL");
+    *out = nullptr;
+    gwn_params p;
+    if (params) p = *params;
+    else gwn_default_params(&p);
+    gwn_status s = check_build_params(dim, &p);
+    if (s) return s;
+    gwn_model *h = new (std::nothrow) gwn_model();
+    if (!h) return fail(GWN_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        s = host_build(p, h->m, err);
+    } catch (const std::bad_alloc &) {
+        s = GWN_ENOMEM;
+        err = "host allocation failed during build";
+    } catch (const std::exception &ex) {
+        s = GWN_EINVAL;
+        err = ex.what();
+    }
+    if (s) {
+        delete h;
+        return fail(s, err);
+    }
+    h->m.device = p.device;
+    if (p.device >= 0) {
+        int ndev = 0;
+        hipError_t e = hipGetDeviceCount(&ndev);
+        if (e != hipSuccess || p.device >= ndev) {
+            delete h;
+            return fail(GWN_EHIP, std::string("no HIP device ") + std::to_string(p.device) +
+                                      (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string()));
+        }
+        s = upload_model(h->m, err);
+        if (s) {
+            h->m.device = -1;
+            delete h;
+            return fail(s, err);
+        }
+    } else {
+        refresh_dev_params(h->m);
+    }
+    *out = h;
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_build2d(const gwn_curves2d *curves, const gwn_params *params, gwn_handle *out)
+{
+    if (!curves) return fail(GWN_EINVAL, "curves is NULL");
+    return build_common(2, params, out, [&](const gwn_params &p, Model &m, std::string &err) {
+        return build2d_host(curves, &p, m, err);
+    });
+}
+
+extern "C" gwn_status gwn_build3d(const gwn_patches3d *patches, const gwn_params *params, gwn_handle *out)
+{
+    if (!patches) return fail(GWN_EINVAL, "patches is NULL");
+    return build_common(3, params, out, [&](const gwn_params &p, Model &m, std::string &err) {
+        return build3d_host(patches, &p, m, err);
+    });
+}
+
+extern "C" gwn_status gwn_set_params(gwn_handle h, const gwn_params *params)
+{
+    if (!h || !params) return fail(GWN_EINVAL, "NULL handle or params");
+    gwn_params p = h->m.params;
+    p.beta = params->beta;
+    p.beta_mixed = params->beta_mixed;
+    p.taylor_order = params->taylor_order;
+    p.precision = params->precision;
+    p.reclass_band = params->reclass_band;
+    p.near_ratio = params->near_ratio;
+    p.eps_q = params->eps_q;
+    gwn_status s = check_query_params(h->m.dim, &p);
+    if (s) return s;
+    h->m.params = p;
+    refresh_dev_params(h->m);
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_get_params(gwn_handle h, gwn_params *out)
+{
+    if (!h || !out) return fail(GWN_EINVAL, "NULL handle or output");
+    *out = h->m.params;
+    return GWN_OK;
+}
+
+static gwn_status check_flag(Model &m)
+{
+    // Lazily read the overflow flag copied back by the previous call.
+    if (!m.flag_event) return GWN_OK;
+    if (hipEventQuery((hipEvent_t)m.flag_event) == hipSuccess && m.h_flag && *m.h_flag) {
+        *m.h_flag = 0;
+        return fail(GWN_EOVERFLOW, "a previous query hit a traversal/near-field stack limit (outputs set to NaN)");
+    }
+    return GWN_OK;
+}
+
+static gwn_status after_launch(Model &m, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(m.h_flag, m.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord((hipEvent_t)m.flag_event, s);
+    if (e != hipSuccess) return hip_fail(e, "flag readback");
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
+                                uint8_t *out_inside, void *stream)
+{
+    if (!h) return fail(GWN_EINVAL, "NULL handle");
+    if (n < 0) return fail(GWN_EINVAL, "n < 0");
+    if (h->m.device < 0) return fail(GWN_EINVAL, "host-only handle cannot be queried");
+    if (n > 0 && (!points || !out_gwn)) return fail(GWN_EINVAL, "NULL points or output");
+    if (n > ((int64_t)1 << 31) - 1024) return fail(GWN_EINVAL, "n too large for one call");
+    gwn_status s = check_flag(h->m);
+    if (s) return s;
+    if (n == 0) return GWN_OK;
+    hipError_t e = hipSetDevice(h->m.device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::vector<Segment> segs{{&h->m, 0, n}};
+    std::string err;
+    s = launch_queries(segs, h->m.dim, points, out_gwn, out_inside, nullptr, stream, err);
+    if (s) return fail(s, err);
+    return after_launch(h->m, stream);
+}
+
+extern "C" gwn_status gwn_query_counters(gwn_handle h, const double *points, int64_t n, int64_t *counters,
+                                         void *stream)
+{
+    if (!h || !counters) return fail(GWN_EINVAL, "NULL handle or counters");
+    if (n < 0) return fail(GWN_EINVAL, "n < 0");
+    if (h->m.device < 0) return fail(GWN_EINVAL, "host-only handle cannot be queried");
+    if (n > 0 && !points) return fail(GWN_EINVAL, "NULL points");
+    hipError_t e = hipSetDevice(h->m.device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = hipMemsetAsync(counters, 0, sizeof(int64_t) * GWN_NCOUNTERS, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
+    if (n == 0) return GWN_OK;
+    std::vector<Segment> segs{{&h->m, 0, n}};
+    std::string err;
+    gwn_status s = launch_queries(segs, h->m.dim, points, nullptr, nullptr, counters, stream, err);
+    if (s) return fail(s, err);
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_query_batch(int32_t n_seg, const gwn_handle *seg_model, const int64_t *seg_offset,
+                                      const double *points, double *out_gwn, uint8_t *out_inside, void *stream)
+{
+    if (n_seg < 0) return fail(GWN_EINVAL, "n_seg < 0");
+    if (n_seg == 0) return GWN_OK;
+    if (!seg_model || !seg_offset) return fail(GWN_EINVAL, "NULL segment arrays");
+    if (seg_offset[0] != 0) return fail(GWN_EINVAL, "seg_offset[0] must be 0");
+    int dim = 0, device = -1;
+    std::vector<Segment> segs;
+    segs.reserve(n_seg);
+    for (int32_t s = 0; s < n_seg; ++s) {
+        gwn_handle h = seg_model[s];
+        if (!h) return fail(GWN_EINVAL, "NULL model in segment " + std::to_string(s));
+        if (h->m.device < 0) return fail(GWN_EINVAL, "host-only handle in segment " + std::to_string(s));
+        if (seg_offset[s + 1] < seg_offset[s]) return fail(GWN_EINVAL, "seg_offset must be non-decreasing");
+        if (dim == 0) { dim = h->m.dim; device = h->m.device; }
+        if (h->m.dim != dim) return fail(GWN_EINVAL, "2D and 3D models cannot share one batch");
+        if (h->m.device != device) return fail(GWN_EINVAL, "all models of a batch must live on one device");
+        gwn_status st = check_flag(h->m);
+        if (st) return st;
+        segs.push_back({&h->m, seg_offset[s], seg_offset[s + 1]});
+    }
+    int64_t n = seg_offset[n_seg];
+    if (n > ((int64_t)1 << 31) - 1024) return fail(GWN_EINVAL, "batch too large for one call");
+    if (n == 0) return GWN_OK;
+    if (!points || !out_gwn) return fail(GWN_EINVAL, "NULL points or output");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    std::string err;
+    gwn_status s = launch_queries(segs, dim, points, out_gwn, out_inside, nullptr, stream, err);
+    if (s) return fail(s, err);
+    for (int32_t k = 0; k < n_seg; ++k) {
+        bool seen = false;
+        for (int32_t j = 0; j < k; ++j) seen |= seg_model[j] == seg_model[k];
+        if (!seen) {
+            s = after_launch(seg_model[k]->m, stream);
+            if (s) return s;
+        }
+    }
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query)
+{
+    if (!h) return fail(GWN_EINVAL, "NULL handle");
+    if (resident) *resident = h->m.arena_bytes + 256;
+    // keys + sort double buffer + permutation + reclass list + sort temp
+    if (per_query) *per_query = 8 + 8 + 4 + 4 + 4 + 16;
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64_t capacity, int64_t *count)
+{
+    if (!h) return fail(GWN_EINVAL, "NULL handle");
+    const Model &m = h->m;
+    const int d = m.dim, nm = n_moments(d);
+    std::vector<double> buf;
+    int64_t items = 0, width = 0;
+    switch (what) {
+    case GWN_I_SUMMARY:
+        buf = {(double)d, (double)m.n_input, (double)m.leaf_src.size(), (double)m.tree.nodes.size(),
+               (double)m.tree.depth, m.diag, m.lo[0], m.hi[0]};
+        items = 1; width = 8;
+        break;
+    case GWN_I_LEAVES: {
+        width = (d == 2) ? 13 : 65;
+        items = (int64_t)m.leaf_src.size();
+        buf.resize(items * width);
+        for (int64_t l = 0; l < items; ++l) {
+            buf[l * width] = (double)m.leaf_src[l];
+            std::memcpy(&buf[l * width + 1], &m.leaf_h[l * (width - 1)], sizeof(double) * (width - 1));
+        }
+        break;
+    }
+    case GWN_I_NODES: {
+        width = 13;
+        items = (int64_t)m.tree.nodes.size();
+        buf.resize(items * width);
+        for (int64_t i = 0; i < items; ++i) {
+            const HostNode &n = m.tree.nodes[i];
+            double *b = &buf[i * width];
+            b[0] = n.is_leaf; b[1] = n.is_leaf ? n.leaf : n.left; b[2] = n.right;
+            for (int a = 0; a < 3; ++a) { b[3 + a] = n.c[a]; b[7 + a] = n.lo[a]; b[10 + a] = n.hi[a]; }
+            b[6] = n.r;
+        }
+        break;
+    }
+    case GWN_I_COMPLEX: {
+        if (d != 2) return fail(GWN_EINVAL, "complex moments exist for 2D models only");
+        width = 2 * (kMaxOrder2D + 1);
+        items = (int64_t)m.tree.nodes.size();
+        buf.assign(m.cmom2.begin(), m.cmom2.end());
+        break;
+    }
+    case GWN_I_MOMENTS:
+    case GWN_I_UNCENTERED: {
+        width = nm;
+        items = (int64_t)m.tree.nodes.size();
+        buf.resize(items * width);
+        for (int64_t i = 0; i < items; ++i) {
+            const auto &v = (what == GWN_I_MOMENTS) ? m.tree.nodes[i].M : m.tree.nodes[i].U;
+            std::memcpy(&buf[i * width], v.data(), sizeof(double) * nm);
+        }
+        break;
+    }
+    default:
+        return fail(GWN_EINVAL, "unknown inspection kind");
+    }
+    if (count) *count = items;
+    if (out && capacity > 0) {
+        int64_t nitems = std::min(capacity, items);
+        std::memcpy(out, buf.data(), sizeof(double) * nitems * width);
+    }
+    return GWN_OK;
+}
+
+extern "C" gwn_status gwn_free(gwn_handle h)
+{
+    if (!h) return GWN_OK;
+    release_device(h->m);
+    delete h;
+    return GWN_OK;
+}
+
+namespace gwn {
+gwn_status profile_control(int enable, double *total_ms, int64_t *launches);
+}
+
+extern "C" gwn_status gwn_profile(int32_t enable, double *total_ms, int64_t *launches)
+{
+    return profile_control(enable, total_ms, launches);
+}
+
+extern "C" const char *gwn_last_error(void) { return g_err.c_str(); }

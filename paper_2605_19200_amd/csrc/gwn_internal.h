@@ -1,0 +1,201 @@
+// Internal definitions of the GWN engine: host model, device record layouts
+// and the launch interface between the host build and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gwn.h"
+
+namespace gwn {
+
+constexpr int kStackDepth = 96;       // per-wave traversal stack (LDS entries)
+constexpr int kBlock = 256;           // threads per block (4 wave64)
+constexpr int kMaxBisectLevel = 48;   // 2D near-field bisection depth
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// ---------------------------------------------------------------------------
+// Device records.  Nodes are stored in depth-first pre-order: the left child
+// of internal node i is i + 1, `right` holds the right child; a leaf stores
+// -1 - leaf_index there.
+// ---------------------------------------------------------------------------
+
+// 2D node, two 128-byte lines.  Internal: centroid, squared AABB half
+// diagonal and the complex form of the centred moments m_0..m_8 with
+// m_k = integral (z - c)^k dz over the cluster's chords (re, im pairs).
+// Leaf: m[0..3] holds the leaf's control-point AABB (lo.x, lo.y, hi.x,
+// hi.y).  The float fields mirror c, r2 and m_0..m_7 for the FP32 pass.
+constexpr int kMaxOrder2D = 8;
+struct alignas(128) Node2 {
+    double c[2];
+    double r2;
+    double m[2 * (kMaxOrder2D + 1)];
+    int32_t right;
+    int32_t degree;
+    float fc[2];
+    float fr2;
+    float fm[2 * kMaxOrder2D];
+    float pad[1];
+};
+static_assert(sizeof(Node2) == 256, "Node2 must be two 128-byte lines");
+
+// 2D leaf primitive: homogeneous cubic control points (w x, w y, w) x 4.
+struct Prim2 {
+    double h[12];
+};
+
+// 3D node, 256 bytes.  Internal: centroid, squared AABB half diagonal and the
+// contracted centred moments used by the order-2 expansion:
+//   t[0..2]   M0_k
+//   t[3..8]   symmetric part of M1: M1_00, M1_11, M1_22, M1_01+M1_10,
+//             M1_02+M1_20, M1_12+M1_21
+//   t[9..11]  e_k = 2 a_k + b_k with a_i = sum_j M2_ijj, b_k = sum_i M2_iik
+//   t[12..21] coefficients of the cubic form sum_ijk M2_ijk s_i s_j s_k on
+//             the monomials s0^3, s1^3, s2^3, s0^2 s1, s0^2 s2, s1^2 s0,
+//             s1^2 s2, s2^2 s0, s2^2 s1, s0 s1 s2
+// Leaf: t[0..5] = AABB lo[3], hi[3]; `aux` = first index of the leaf's
+// precomputed quadrature nodes, `count` = their number, `right` = -1 - leaf.
+struct alignas(128) Node3 {
+    double c[3];
+    double r2;
+    double t[22];
+    int32_t right;
+    int32_t count;
+    int64_t aux;
+    float fc[3];
+    float fr2;
+    float ft[22];
+    float pad[6];
+};
+static_assert(sizeof(Node3) == 384, "Node3 layout");
+
+// 3D leaf: homogeneous bicubic control net, 16 x (wx, wy, wz, w), u-major,
+// plus the trim-curve range and the untrimmed flag.
+struct Prim3 {
+    double h[64];
+    int32_t trim_begin;   // index into the model's trim-curve array
+    int32_t trim_count;   // 0 = untrimmed (whole square)
+    int32_t pad[2];
+};
+
+// Trim curve in (u, v), homogeneous, degree 1 or 2 stored as 3 points
+// (degree 1 is elevated to 2).
+struct Trim3 {
+    double h[9];          // (w u, w v, w) x 3
+    double pad;
+};
+
+// Precomputed far-rule quadrature node of a 3D leaf: position and weighted
+// normal (Green-scattered Gauss-Legendre node, Sec. 3.1).
+struct QNode3 {
+    double x[3];
+    double n[3];
+};
+
+// ---------------------------------------------------------------------------
+// Kernel-side model descriptor (passed by value / stored in device arrays).
+// ---------------------------------------------------------------------------
+struct DevModel {
+    const void *nodes;      // Node2* or Node3*
+    const void *prims;      // Prim2* or Prim3*
+    const void *trims;      // Trim3* (3D)
+    const void *qnodes;     // QNode3* (3D)
+    int32_t *flag;          // overflow flag (device)
+    int32_t dim;
+    int32_t n_nodes;
+    int32_t order;
+    int32_t precision;
+    double beta2;           // beta^2 (FP64 form / reclassification)
+    double beta2_mixed;     // beta_mixed^2 (FP32 pass)
+    double band;            // reclassification band
+    double lo[3];           // bbox for space-filling-curve keys
+    double inv_ext[3];
+    double eps_on;          // absolute on-boundary distance
+    double near_ratio2;     // 3D: (near_ratio)^2 factor on squared AABB diagonal
+    double eps_q;           // 3D near-field tolerance
+    int32_t gl_n;           // 3D GL nodes
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side tree (shared by 2D and 3D builds).
+// ---------------------------------------------------------------------------
+struct HostNode {
+    int is_leaf = 0;
+    int left = -1, right = -1;   // DFS indices of children (internal)
+    int leaf = -1;               // leaf index (leaf)
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double c[3] = {0, 0, 0};
+    double r = 0;
+    double wsum = 0;             // centroid weight (chord length / area)
+    double wc[3] = {0, 0, 0};    // weighted centroid sum
+    std::vector<double> U;       // uncentered moments: M0[d], M1[d*d], M2[d^3]
+    std::vector<double> M;       // centred moments, same layout
+};
+
+struct HostTree {
+    int dim = 2;
+    std::vector<HostNode> nodes;  // DFS pre-order, root = 0
+    int depth = 0;
+};
+
+// Build the Karras BVH over `n` leaves (AABBs lo/hi stride 3), sum the leaves'
+// uncentered moments up the tree and centre them in place (Alg. 1
+// ConstructBVH, SumUncenteredMomentsUpTree, CenterMomentsInPlace).
+// leafU: n * nm uncentered moments, leafW: n centroid weights, leafWC: n * 3
+// weighted centroid sums.  Returns false with `err` set on failure.
+bool build_tree(int dim, int n, const double *lo, const double *hi, const double *leafU,
+                const double *leafW, const double *leafWC, const double *model_lo,
+                const double *model_hi, HostTree &tree, std::string &err);
+
+inline int n_moments(int dim) { return dim + dim * dim + dim * dim * dim; }
+
+// ---------------------------------------------------------------------------
+// Host model (behind gwn_handle).
+// ---------------------------------------------------------------------------
+struct Model {
+    int dim = 2;
+    gwn_params params{};
+    int64_t n_input = 0;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double diag = 0;
+    HostTree tree;
+    // leaves in BVH leaf order
+    std::vector<int64_t> leaf_src;
+    std::vector<double> leaf_h;       // 12 (2D) or 64 (3D) doubles per leaf
+    std::vector<int32_t> leaf_degree; // 2D original degree
+    std::vector<double> cmom2;        // 2D: per node 2*(kMaxOrder2D+1) centred complex moments
+    // 3D only
+    std::vector<Trim3> trims;
+    std::vector<int32_t> leaf_trim_begin, leaf_trim_count;
+    std::vector<QNode3> qnodes;
+    std::vector<int64_t> leaf_q_begin, leaf_q_count;
+    // device
+    int device = -1;
+    void *d_arena = nullptr;
+    int64_t arena_bytes = 0;
+    int32_t *d_flag = nullptr;
+    int32_t *h_flag = nullptr;     // pinned
+    void *flag_event = nullptr;    // hipEvent_t
+    DevModel dev{};
+};
+
+// builders (host)
+gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, std::string &err);
+gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, std::string &err);
+// upload to device and fill m.dev
+gwn_status upload_model(Model &m, std::string &err);
+void refresh_dev_params(Model &m);
+void release_device(Model &m);
+
+// query launchers (query.hip)
+struct Segment {
+    const Model *model;
+    int64_t q_begin, q_end;   // rows of the points/output arrays
+};
+gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const double *points,
+                          double *out_gwn, uint8_t *out_inside, int64_t *counters, void *stream,
+                          std::string &err);
+
+}  // namespace gwn

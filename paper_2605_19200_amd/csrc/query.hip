@@ -1,0 +1,618 @@
+// Query phase of Alg. 1 on gfx950: space-filling-curve ordering of the
+// queries, wavefront-coherent BVH traversal with the far-field Taylor
+// approximation (Eq. taylor) and direct leaf evaluation (Sec. 3.3), the
+// mixed-precision pass with FP64 reclassification near w = 0.5, and batched
+// multi-model launches.
+//
+// Traversal scheme.  One lane per query; the 64 queries of a wave (adjacent
+// along a Morton curve) walk the tree together with ONE stack of
+// (node, lane mask) entries in LDS.  At an internal node each lane in the
+// mask applies its own far test ||q - c||^2 > beta^2 r^2; lanes for which the
+// cluster is far add its Taylor term, the others continue into the children
+// (pushed with the mask of those lanes).  A lane therefore visits exactly the
+// nodes of its own per-query depth-first (left child first) traversal, in the
+// same order, so every result is bitwise independent of its wave mates.
+// Node records are read at wave-uniform addresses (scalar loads).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "gwn_internal.h"
+
+namespace gwn {
+
+constexpr int kMaxSeg = 32;
+constexpr int kMaxModels = 8;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kMaxBisectIter = 16384;
+
+struct LaunchTable {
+    int32_t n_seg;
+    int32_t n_waves;
+    int32_t seg_model[kMaxSeg];
+    int32_t woff[kMaxSeg + 1];
+    int64_t qoff[kMaxSeg + 1];
+    DevModel models[kMaxModels];
+};
+
+struct Ctr {
+    long long v[GWN_NCOUNTERS];
+};
+
+__device__ __forceinline__ int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------------------
+// space-filling-curve keys
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t part1by1(uint64_t x)  // 24 bits -> 48
+{
+    x &= 0xffffffull;
+    x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+    x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+    x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t part1by2(uint64_t x)  // 16 bits -> 48
+{
+    x &= 0xffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t quantize(double v, double lo, double inv, double maxq)
+{
+    double t = (v - lo) * inv;
+    t = fmin(fmax(t, 0.0), 1.0);  // NaN -> 0 or 1
+    return (uint64_t)(t * maxq);
+}
+
+__device__ __forceinline__ int find_seg(const LaunchTable &T, int64_t row)
+{
+    int lo = 0, hi = T.n_seg - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T.qoff[mid] <= row) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(LaunchTable T, int dim, const double *__restrict__ pts,
+                                                 uint64_t *__restrict__ keys, int32_t *__restrict__ vals,
+                                                 int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int s = find_seg(T, i);
+    const DevModel &M = T.models[T.seg_model[s]];
+    uint64_t code;
+    if (dim == 2) {
+        uint64_t x = quantize(pts[2 * i], M.lo[0], M.inv_ext[0], 16777215.0);
+        uint64_t y = quantize(pts[2 * i + 1], M.lo[1], M.inv_ext[1], 16777215.0);
+        code = part1by1(x) | (part1by1(y) << 1);
+    } else {
+        uint64_t x = quantize(pts[3 * i], M.lo[0], M.inv_ext[0], 65535.0);
+        uint64_t y = quantize(pts[3 * i + 1], M.lo[1], M.inv_ext[1], 65535.0);
+        uint64_t z = quantize(pts[3 * i + 2], M.lo[2], M.inv_ext[2], 65535.0);
+        code = part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+    }
+    keys[i] = ((uint64_t)s << 48) | code;
+    vals[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// 2D leaf: direct evaluation (Sec. 3.3)
+// ---------------------------------------------------------------------------
+// Signed angle at q (the origin of the translated frame) from a to b; 0 when
+// q lies on the segment (the direct value of a straight piece through q).
+__device__ __forceinline__ double chord_angle(double ax, double ay, double bx, double by)
+{
+    double cr = ax * by - ay * bx;
+    double dt = ax * bx + ay * by;
+    if (cr == 0.0 && dt <= 0.0) return 0.0;
+    return atan2(cr, dt);
+}
+
+__device__ __forceinline__ double lerp_exact(double a, double b, double t, double s)
+{
+    return fma(t, b, s * a);   // exact at t = 0 and t = 1
+}
+
+// Direct angle subtended by one cubic leaf at q, in radians.
+// If q is outside the leaf's control-point AABB, the chord angle is exact
+// (chord substitution, Sec. 3.1; AABB test instead of a hull test, Sec. 3.3).
+// Otherwise the curve is bisected toward q: pieces are enumerated depth first
+// as dyadic parameter intervals [k 2^-L, (k+1) 2^-L] (no stack: the next
+// interval follows from (L, k)), each piece's control points are obtained by
+// blossoming the leaf's control points, a piece whose AABB excludes q adds
+// its chord angle, and a piece that still contains q when it is smaller than
+// eps_on or after kMaxBisectLevel halvings (q on the curve) adds the mean of
+// its two one-sided limits (the direct value).
+// The end point of each piece is carried to the next so consecutive chords
+// share their end points bit for bit.
+template <bool COUNT>
+__device__ double leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__ prims, double qx, double qy,
+                         double eps_on, Ctr &ctr, bool &overflow)
+{
+    const int leaf = -1 - nd->right;
+    const Prim2 *P = prims + leaf;
+    double bx[4], by[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double w = P->h[3 * i + 2];
+        bx[i] = fma(-qx, w, P->h[3 * i]);
+        by[i] = fma(-qy, w, P->h[3 * i + 1]);
+    }
+    if (COUNT) ctr.v[GWN_C_LEAVES]++;
+    const bool outside = qx < nd->m[0] || qy < nd->m[1] || qx > nd->m[2] || qy > nd->m[3];
+    if (outside || nd->degree == 1) {
+        if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
+        return chord_angle(bx[0], by[0], bx[3], by[3]);
+    }
+    if (!(fabs(qx) < INFINITY && fabs(qy) < INFINITY)) return NAN;
+    // On-boundary rule: a piece whose control points all lie within eps_on
+    // of q (|x_i| / w_i < eps_on with w_i >= the leaf's smallest weight) is
+    // terminal.
+    const double wmin = fmin(fmin(P->h[2], P->h[5]), fmin(P->h[8], P->h[11]));
+    const double on_tol = eps_on * wmin;
+    double sum = 0.0;
+    int level = 1;
+    uint64_t k = 0;
+    double p0x = bx[0], p0y = by[0];
+    for (int it = 0;; ++it) {
+        if (it >= kMaxBisectIter) { overflow = true; return NAN; }
+        const double inv = ldexp(1.0, -level);
+        const double t0 = (double)k * inv, t1 = (double)(k + 1) * inv;
+        const double s0 = 1.0 - t0, s1 = 1.0 - t1;
+        // blossom levels at t0
+        double ax1[3], ay1[3], ax2[2], ay2[2], cx2[2], cy2[2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ax1[i] = lerp_exact(bx[i], bx[i + 1], t0, s0);
+            ay1[i] = lerp_exact(by[i], by[i + 1], t0, s0);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            ax2[i] = lerp_exact(ax1[i], ax1[i + 1], t0, s0);   // (t0, t0)
+            ay2[i] = lerp_exact(ay1[i], ay1[i + 1], t0, s0);
+            cx2[i] = lerp_exact(ax1[i], ax1[i + 1], t1, s1);   // (t0, t1)
+            cy2[i] = lerp_exact(ay1[i], ay1[i + 1], t1, s1);
+        }
+        const double p1x = lerp_exact(ax2[0], ax2[1], t1, s1), p1y = lerp_exact(ay2[0], ay2[1], t1, s1);
+        const double p2x = lerp_exact(cx2[0], cx2[1], t1, s1), p2y = lerp_exact(cy2[0], cy2[1], t1, s1);
+        // end point b(t1, t1, t1)
+        double ex1[3], ey1[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ex1[i] = lerp_exact(bx[i], bx[i + 1], t1, s1);
+            ey1[i] = lerp_exact(by[i], by[i + 1], t1, s1);
+        }
+        const double e20 = lerp_exact(ex1[0], ex1[1], t1, s1), e21 = lerp_exact(ex1[1], ex1[2], t1, s1);
+        const double f20 = lerp_exact(ey1[0], ey1[1], t1, s1), f21 = lerp_exact(ey1[1], ey1[2], t1, s1);
+        const double p3x = lerp_exact(e20, e21, t1, s1), p3y = lerp_exact(f20, f21, t1, s1);
+        if (COUNT) ctr.v[GWN_C_PIECES]++;
+        const double xmn = fmin(fmin(p0x, p1x), fmin(p2x, p3x)), xmx = fmax(fmax(p0x, p1x), fmax(p2x, p3x));
+        const double ymn = fmin(fmin(p0y, p1y), fmin(p2y, p3y)), ymx = fmax(fmax(p0y, p1y), fmax(p2y, p3y));
+        const bool out = xmn > 0.0 || xmx < 0.0 || ymn > 0.0 || ymx < 0.0;
+        const bool on = fmax(fmax(-xmn, xmx), fmax(-ymn, ymx)) < on_tol;
+        if (!out && !on && level < kMaxBisectLevel) {
+            ++level;
+            k <<= 1;
+            continue;
+        }
+        {
+            // Outside: the chord angle is exact.  Terminal piece still holding
+            // q (within eps_on, or at the depth limit): q is on the curve to
+            // tolerance, and the piece takes the mean of its two one-sided
+            // limits, i.e. its chord angle with the jump of +-pi removed
+            // when q lies between its end points.
+            double a = chord_angle(p0x, p0y, p3x, p3y);
+            if (!out && fabs(a) > 0.5 * kPi) a -= copysign(kPi, a);
+            sum += a;
+            if (COUNT) ctr.v[GWN_C_ANGLES]++;
+        }
+        p0x = p3x;
+        p0y = p3y;
+        while (level > 0 && (k & 1)) { k >>= 1; --level; }
+        if (level == 0) break;
+        ++k;
+    }
+    return sum;
+}
+
+// Far-field contribution of an accepted 2D cluster, as an angle in radians.
+// The order-p Taylor expansion of Eq. taylor about the centroid c equals
+// -Im( sum_{k<=p} m_k u^{k+1} ) with u = 1/(q - c) and m_k = int (z - c)^k dz
+// (complex form of the centred moments; Horner in u).
+template <typename T>
+__device__ __forceinline__ T taylor2d(T dx, T dy, T d2, const T *m, int order)
+{
+    const T inv = T(1) / d2;
+    const T ur = dx * inv, ui = -dy * inv;
+    T tr = m[2 * order], ti = m[2 * order + 1];
+    for (int k = order - 1; k >= 0; --k) {
+        const T nr = m[2 * k] + ur * tr - ui * ti;
+        const T ni = m[2 * k + 1] + ur * ti + ui * tr;
+        tr = nr;
+        ti = ni;
+    }
+    return -(ur * ti + ui * tr);   // -Im(u * t)
+}
+
+struct StackLDS {
+    int node[kWavesPerBlock][kStackDepth];
+    unsigned long long mask[kWavesPerBlock][kStackDepth];
+};
+
+// Traversal of one wave over a 2D model.  `mask`: lanes taking part (wave
+// uniform).  F32: far-field tests and Taylor terms in FP32 (mixed form).
+template <bool F32, bool COUNT>
+__device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t mask, StackLDS &S, int w,
+                             Ctr &ctr, bool &overflow)
+{
+    const Node2 *__restrict__ nodes = (const Node2 *)M.nodes;
+    const Prim2 *__restrict__ prims = (const Prim2 *)M.prims;
+    const int lane = lane_id();
+    const bool me = (mask >> lane) & 1;
+    const float qxf = (float)qx, qyf = (float)qy;
+    const double beta2 = F32 ? M.beta2_mixed : M.beta2;
+    const float beta2f = (float)M.beta2_mixed;
+    double acc = 0.0;
+    int cur = 0;
+    uint64_t curmask = mask;
+    int sp = 0;
+    if (M.n_nodes == 0) return 0.0;
+    while (true) {
+        const Node2 *nd = nodes + cur;
+        const int right = nd->right;
+        const bool active = (curmask >> lane) & 1;
+        if (right < 0) {
+            if (active) acc += leaf2d<COUNT>(nd, prims, qx, qy, M.eps_on, ctr, overflow);
+        } else {
+            bool far = false;
+            if (active) {
+                if (COUNT) ctr.v[GWN_C_NODES]++;
+                if (F32) {
+                    const float dx = qxf - nd->fc[0], dy = qyf - nd->fc[1];
+                    const float d2 = dx * dx + dy * dy;
+                    far = d2 > beta2f * nd->fr2;
+                    if (far) acc += (double)taylor2d<float>(dx, dy, d2, nd->fm, min(M.order, kMaxOrder2D - 1));
+                } else {
+                    const double dx = qx - nd->c[0], dy = qy - nd->c[1];
+                    const double d2 = dx * dx + dy * dy;
+                    far = d2 > beta2 * nd->r2;
+                    if (far) acc += taylor2d<double>(dx, dy, d2, nd->m, M.order);
+                }
+                if (COUNT && far) ctr.v[GWN_C_FAR]++;
+            }
+            const uint64_t farmask = __ballot(active && far);
+            const uint64_t nearmask = curmask & ~farmask;
+            if (nearmask) {
+                S.node[w][sp] = right;
+                S.mask[w][sp] = nearmask;
+                ++sp;
+                cur = cur + 1;
+                curmask = nearmask;
+                continue;
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        cur = uniform_i(S.node[w][sp]);
+        curmask = uniform_u64(S.mask[w][sp]);
+    }
+    (void)me;
+    return acc * (1.0 / (2.0 * kPi));
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void flush_counters(Ctr &ctr, long long *counters)
+{
+    if (!COUNT) return;
+#pragma unroll
+    for (int k = 0; k < GWN_NCOUNTERS; ++k) {
+        long long v = ctr.v[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane_id() == 0 && v) atomicAdd((unsigned long long *)&counters[k], (unsigned long long)v);
+    }
+}
+
+// Main query kernel (2D): one wave per 64 consecutive sorted queries of one
+// segment.  Mixed-precision segments run the FP32 far-field pass and append
+// queries with |w - 0.5| < band to the reclassification list.
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double *__restrict__ pts,
+                                                    const int32_t *__restrict__ perm, double *__restrict__ out_w,
+                                                    uint8_t *__restrict__ out_in, int32_t *__restrict__ reclass,
+                                                    int32_t *__restrict__ reclass_n, long long *counters)
+{
+    __shared__ StackLDS S;
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int wave = blockIdx.x * kWavesPerBlock + w;
+    if (wave >= T.n_waves) return;
+    int s = 0;
+    {
+        int lo = 0, hi = T.n_seg - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (T.woff[mid] <= wave) lo = mid; else hi = mid - 1;
+        }
+        s = uniform_i(lo);
+    }
+    const DevModel &M = T.models[T.seg_model[s]];
+    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * 64 + lane;
+    const bool valid = pos < T.qoff[s + 1];
+    const int row = valid ? perm[pos] : 0;
+    const double qx = valid ? pts[2 * (int64_t)row] : 0.0;
+    const double qy = valid ? pts[2 * (int64_t)row + 1] : 0.0;
+    const uint64_t mask = __ballot(valid);
+    Ctr ctr;
+#pragma unroll
+    for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
+    bool overflow = false;
+    double wq;
+    const bool mixed = M.precision == GWN_MIXED;
+    if (mixed) wq = traverse2d<true, COUNT>(M, qx, qy, mask, S, w, ctr, overflow);
+    else wq = traverse2d<false, COUNT>(M, qx, qy, mask, S, w, ctr, overflow);
+    if (valid) {
+        if (overflow) {
+            wq = NAN;
+            atomicOr(M.flag, 1);
+            if (COUNT) ctr.v[GWN_C_OVERFLOW]++;
+        }
+        if (mixed && fabs(wq - 0.5) < M.band) {
+            if (COUNT) ctr.v[GWN_C_RECLASS]++;
+            if (reclass) reclass[atomicAdd(reclass_n, 1)] = row;
+        }
+        if (out_w) out_w[row] = wq;
+        if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
+    }
+    flush_counters<COUNT>(ctr, counters);
+}
+
+// FP64 re-evaluation of the reclassification list (mixed form).  Lanes of a
+// wave may belong to different models; each distinct model is traversed in
+// turn with the mask of its lanes.
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_reclass2d(LaunchTable T, const double *__restrict__ pts,
+                                                      const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ list_n, double *__restrict__ out_w,
+                                                      uint8_t *__restrict__ out_in, long long *counters)
+{
+    __shared__ StackLDS S;
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int count = *list_n;
+    if ((int64_t)blockIdx.x * kBlock + w * 64 >= count) return;
+    const bool valid = i < count;
+    const int row = valid ? list[i] : 0;
+    const int seg = valid ? find_seg(T, row) : 0;
+    const double qx = valid ? pts[2 * (int64_t)row] : 0.0;
+    const double qy = valid ? pts[2 * (int64_t)row + 1] : 0.0;
+    Ctr ctr;
+#pragma unroll
+    for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
+    bool overflow = false;
+    double wq = 0.0;
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const int mseg = __shfl(seg, leader);
+        const int model = uniform_i(T.seg_model[mseg]);
+        const uint64_t mine = __ballot(valid && T.seg_model[seg] == model) & todo;
+        const DevModel &M = T.models[model];
+        double r = traverse2d<false, COUNT>(M, qx, qy, mine, S, w, ctr, overflow);
+        if ((mine >> lane) & 1) wq = r;
+        todo &= ~mine;
+    }
+    if (valid) {
+        if (overflow) {
+            wq = NAN;
+            atomicOr(T.models[T.seg_model[seg]].flag, 1);
+        }
+        if (out_w) out_w[row] = wq;
+        if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
+    }
+    flush_counters<COUNT>(ctr, counters);
+}
+
+// 3D kernels live in query3d.hip
+gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t *perm, double *out_w,
+                          uint8_t *out_in, int32_t *reclass, int32_t *reclass_n, long long *counters,
+                          bool any_mixed, hipStream_t stream, std::string &err);
+
+// ---------------------------------------------------------------------------
+// host launcher
+// ---------------------------------------------------------------------------
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+
+static void prof_begin(hipStream_t s, hipEvent_t &a)
+{
+    a = nullptr;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+    (void)hipEventRecord(a, s);
+}
+
+static void prof_end(hipStream_t s, hipEvent_t a)
+{
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_events.emplace_back(a, b);
+}
+
+gwn_status profile_control(int enable, double *total_ms, int64_t *launches)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double ms = 0.0;
+    int64_t cnt = 0;
+    for (auto &ev : g_prof_events) {
+        float t = 0.f;
+        if (hipEventSynchronize(ev.second) == hipSuccess && hipEventElapsedTime(&t, ev.first, ev.second) == hipSuccess) {
+            ms += t;
+            ++cnt;
+        }
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    g_prof_events.clear();
+    g_prof_on = enable != 0;
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = cnt;
+    return GWN_OK;
+}
+static gwn_status hip_err(hipError_t e, const char *what, std::string &err)
+{
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return GWN_EHIP;
+}
+
+static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size_t s1, int dim,
+                               const double *points, double *out_gwn, uint8_t *out_inside, int64_t *counters,
+                               hipStream_t stream, std::string &err)
+{
+    LaunchTable T;
+    std::memset(&T, 0, sizeof T);
+    std::vector<const Model *> models;
+    T.n_seg = (int32_t)(s1 - s0);
+    const int64_t row0 = segs[s0].q_begin;
+    int64_t q = 0;
+    int32_t wv = 0;
+    bool any_mixed = false;
+    for (size_t k = s0; k < s1; ++k) {
+        const Model *m = segs[k].model;
+        int mi = -1;
+        for (size_t j = 0; j < models.size(); ++j)
+            if (models[j] == m) mi = (int)j;
+        if (mi < 0) {
+            mi = (int)models.size();
+            models.push_back(m);
+            T.models[mi] = m->dev;
+        }
+        any_mixed |= m->params.precision == GWN_MIXED;
+        const int j = (int)(k - s0);
+        T.seg_model[j] = mi;
+        T.qoff[j] = q;
+        T.woff[j] = wv;
+        const int64_t cnt = segs[k].q_end - segs[k].q_begin;
+        q += cnt;
+        wv += (int32_t)((cnt + 63) / 64);
+    }
+    T.qoff[T.n_seg] = q;
+    T.woff[T.n_seg] = wv;
+    T.n_waves = wv;
+    const int64_t n = q;
+    if (n == 0) return GWN_OK;
+    const double *pts = points + row0 * dim;
+    double *ow = out_gwn ? out_gwn + row0 : nullptr;
+    uint8_t *oi = out_inside ? out_inside + row0 : nullptr;
+
+    // scratch: keys[2n] (u64), vals[2n] (i32), reclass list [n] + count, sort temp
+    size_t temp_bytes = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                                      (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 54, stream);
+    if (e != hipSuccess) return hip_err(e, "radix sort sizing", err);
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t b_keys = al(sizeof(uint64_t) * n), b_vals = al(sizeof(int32_t) * n);
+    const size_t total = 2 * b_keys + 2 * b_vals + b_vals + 256 + al(temp_bytes);
+    char *scratch = nullptr;
+    e = hipMallocAsync((void **)&scratch, total, stream);
+    if (e != hipSuccess) return hip_err(e, "hipMallocAsync scratch", err);
+    uint64_t *k_in = (uint64_t *)scratch, *k_out = (uint64_t *)(scratch + b_keys);
+    int32_t *v_in = (int32_t *)(scratch + 2 * b_keys), *v_out = (int32_t *)(scratch + 2 * b_keys + b_vals);
+    int32_t *list = (int32_t *)(scratch + 2 * b_keys + 2 * b_vals);
+    int32_t *list_n = (int32_t *)(scratch + 2 * b_keys + 3 * b_vals);
+    void *temp = scratch + 2 * b_keys + 3 * b_vals + 256;
+
+    const int grid_q = (int)((n + kBlock - 1) / kBlock);
+    gwn_status st = GWN_OK;
+    hipLaunchKernelGGL(k_keys, dim3(grid_q), dim3(kBlock), 0, stream, T, dim, pts, k_in, v_in, n);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k_in, k_out, v_in, v_out, (int)n, 0, 54, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(list_n, 0, sizeof(int32_t), stream);
+    if (e != hipSuccess) st = hip_err(e, "key/sort launch", err);
+    if (!st) {
+        hipEvent_t ev0;
+        prof_begin(stream, ev0);
+        if (dim == 2) {
+            const int grid_w = (T.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+            if (counters)
+                hipLaunchKernelGGL(k_query2d<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
+                                   any_mixed ? list : nullptr, list_n, (long long *)counters);
+            else
+                hipLaunchKernelGGL(k_query2d<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
+                                   any_mixed ? list : nullptr, list_n, nullptr);
+            e = hipGetLastError();
+            if (e == hipSuccess && any_mixed) {
+                if (counters)
+                    hipLaunchKernelGGL(k_reclass2d<true>, dim3(grid_q), dim3(kBlock), 0, stream, T, pts, list, list_n,
+                                       ow, oi, (long long *)counters);
+                else
+                    hipLaunchKernelGGL(k_reclass2d<false>, dim3(grid_q), dim3(kBlock), 0, stream, T, pts, list,
+                                       list_n, ow, oi, nullptr);
+                e = hipGetLastError();
+            }
+            if (e != hipSuccess) st = hip_err(e, "query launch", err);
+        } else {
+            st = launch_query3d(T, pts, v_out, ow, oi, any_mixed ? list : nullptr, list_n, (long long *)counters,
+                                any_mixed, stream, err);
+        }
+        prof_end(stream, ev0);
+    }
+    hipError_t e2 = hipFreeAsync(scratch, stream);
+    if (!st && e2 != hipSuccess) st = hip_err(e2, "hipFreeAsync scratch", err);
+    return st;
+}
+
+gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const double *points, double *out_gwn,
+                          uint8_t *out_inside, int64_t *counters, void *stream, std::string &err)
+{
+    hipStream_t s = (hipStream_t)stream;
+    size_t a = 0;
+    while (a < segs.size()) {
+        // chunk: <= kMaxSeg segments, <= kMaxModels distinct models, contiguous rows
+        std::vector<const Model *> seen;
+        size_t b = a;
+        while (b < segs.size() && b - a < (size_t)kMaxSeg) {
+            const Model *m = segs[b].model;
+            bool known = std::find(seen.begin(), seen.end(), m) != seen.end();
+            if (!known && seen.size() == (size_t)kMaxModels) break;
+            if (!known) seen.push_back(m);
+            if (b > a && segs[b].q_begin != segs[b - 1].q_end) break;
+            ++b;
+        }
+        gwn_status st = launch_chunk(segs, a, b, dim, points, out_gwn, out_inside, counters, s, err);
+        if (st) return st;
+        a = b;
+    }
+    return GWN_OK;
+}
+
+}  // namespace gwn

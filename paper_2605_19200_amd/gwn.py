@@ -1,0 +1,269 @@
+"""Python binding of the C ABI in ``include/gwn.h`` (argument marshalling only).
+
+Functions keep the C names (``gwn_build2d``, ``gwn_query``, ...).  Device
+buffers are torch tensors on a ROCm device; only their data pointers and the
+HIP stream handle cross the boundary.  Every step of the query path runs in
+the HIP library ``libgwn.so``; if it is missing this module raises at import
+time of the library (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgwn.so")
+
+GWN_OK, GWN_EINVAL, GWN_ENOMEM, GWN_EHIP, GWN_EUNSUPPORTED, GWN_EOVERFLOW = range(6)
+GWN_FP64, GWN_MIXED = 0, 1
+COUNTER_NAMES = ["nodes", "far", "leaves", "leaf_fast", "pieces", "angles", "reclass", "overflow"]
+GWN_NCOUNTERS = len(COUNTER_NAMES)
+GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX = range(6)
+
+EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_set_params", "gwn_get_params", "gwn_query",
+            "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
+            "gwn_free", "gwn_last_error"]
+
+
+class GwnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gwn status {status}: {msg}")
+        self.status = status
+
+
+class gwn_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("beta_mixed", ctypes.c_double), ("taylor_order", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reclass_band", ctypes.c_double), ("max_diag_frac", ctypes.c_double),
+                ("eps_on", ctypes.c_double), ("gl_nodes", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("near_ratio", ctypes.c_double), ("eps_q", ctypes.c_double)]
+
+
+class gwn_curves2d(ctypes.Structure):
+    _fields_ = [("n_curves", ctypes.c_int64), ("degree", ctypes.c_void_p), ("cp_offset", ctypes.c_void_p),
+                ("cp_xy", ctypes.c_void_p), ("cp_w", ctypes.c_void_p)]
+
+
+class gwn_patches3d(ctypes.Structure):
+    _fields_ = [("n_patches", ctypes.c_int64), ("cp_xyz", ctypes.c_void_p), ("cp_w", ctypes.c_void_p),
+                ("trim_offset", ctypes.c_void_p), ("trim_degree", ctypes.c_void_p),
+                ("trim_cp_offset", ctypes.c_void_p), ("trim_cp_uv", ctypes.c_void_p), ("trim_cp_w", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() "
+                               "(or python paper_2605_19200_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.gwn_default_params.argtypes = [ctypes.POINTER(gwn_params)]
+        L.gwn_default_params.restype = None
+        for name, args in [
+            ("gwn_build2d", [ctypes.POINTER(gwn_curves2d), ctypes.POINTER(gwn_params), ctypes.POINTER(vp)]),
+            ("gwn_build3d", [ctypes.POINTER(gwn_patches3d), ctypes.POINTER(gwn_params), ctypes.POINTER(vp)]),
+            ("gwn_set_params", [vp, ctypes.POINTER(gwn_params)]),
+            ("gwn_get_params", [vp, ctypes.POINTER(gwn_params)]),
+            ("gwn_query", [vp, vp, i64, vp, vp, vp]),
+            ("gwn_query_batch", [i32, vp, vp, vp, vp, vp, vp]),
+            ("gwn_query_counters", [vp, vp, i64, vp, vp]),
+            ("gwn_model_bytes", [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+            ("gwn_inspect", [vp, i32, vp, i64, ctypes.POINTER(i64)]),
+            ("gwn_free", [vp]),
+            ("gwn_profile", [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+        ]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        L.gwn_last_error.argtypes = []
+        L.gwn_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != GWN_OK:
+        raise GwnError(status, lib().gwn_last_error().decode(errors="replace"))
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def gwn_default_params(**overrides) -> gwn_params:
+    p = gwn_params()
+    lib().gwn_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def gwn_build2d(curves, params: gwn_params | None = None):
+    """Build a 2D model from a ``workloads.Curves2D``; returns the handle."""
+    deg, off = _np(curves.degree, np.int32), _np(curves.cp_offset, np.int64)
+    xy, w = _np(curves.cp_xy, np.float64), _np(curves.cp_w, np.float64)
+    c = gwn_curves2d(curves.n, _p(deg), _p(off), _p(xy), _p(w))
+    h = ctypes.c_void_p()
+    _check(lib().gwn_build2d(ctypes.byref(c), ctypes.byref(params) if params else None, ctypes.byref(h)))
+    return h
+
+
+def gwn_build3d(patches, params: gwn_params | None = None):
+    """Build a 3D model from a ``workloads.Patches3D``; returns the handle."""
+    arrs = [_np(patches.cp_xyz, np.float64), _np(patches.cp_w, np.float64), _np(patches.trim_offset, np.int64),
+            _np(patches.trim_degree, np.int32), _np(patches.trim_cp_offset, np.int64),
+            _np(patches.trim_cp_uv, np.float64), _np(patches.trim_cp_w, np.float64)]
+    c = gwn_patches3d(patches.n, *[_p(a) for a in arrs])
+    h = ctypes.c_void_p()
+    _check(lib().gwn_build3d(ctypes.byref(c), ctypes.byref(params) if params else None, ctypes.byref(h)))
+    return h
+
+
+def gwn_set_params(h, params: gwn_params):
+    _check(lib().gwn_set_params(h, ctypes.byref(params)))
+
+
+def gwn_get_params(h) -> gwn_params:
+    p = gwn_params()
+    _check(lib().gwn_get_params(h, ctypes.byref(p)))
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def gwn_query(h, points, out_gwn, out_inside=None, stream=None):
+    """points: device float64 tensor [n, dim]; out_gwn: device float64 [n];
+    out_inside: device uint8 [n] or None.  Asynchronous on `stream`."""
+    n = points.shape[0]
+    _check(lib().gwn_query(h, ctypes.c_void_p(points.data_ptr()), n, ctypes.c_void_p(out_gwn.data_ptr()),
+                           ctypes.c_void_p(out_inside.data_ptr()) if out_inside is not None else None,
+                           _stream_ptr(stream)))
+
+
+def gwn_query_batch(models, seg_offset, points, out_gwn, out_inside=None, stream=None):
+    """models: list of handles (one per segment); seg_offset: host int64
+    [n_seg + 1]; points/out_*: device tensors covering all segments."""
+    n_seg = len(models)
+    arr = (ctypes.c_void_p * max(n_seg, 1))(*[m.value if isinstance(m, ctypes.c_void_p) else m for m in models])
+    off = _np(seg_offset, np.int64)
+    _check(lib().gwn_query_batch(n_seg, ctypes.cast(arr, ctypes.c_void_p), _p(off),
+                                 ctypes.c_void_p(points.data_ptr()), ctypes.c_void_p(out_gwn.data_ptr()),
+                                 ctypes.c_void_p(out_inside.data_ptr()) if out_inside is not None else None,
+                                 _stream_ptr(stream)))
+
+
+def gwn_query_counters(h, points, counters, stream=None):
+    """counters: device int64 tensor [GWN_NCOUNTERS] (overwritten)."""
+    _check(lib().gwn_query_counters(h, ctypes.c_void_p(points.data_ptr()), points.shape[0],
+                                    ctypes.c_void_p(counters.data_ptr()), _stream_ptr(stream)))
+
+
+def gwn_model_bytes(h):
+    r, q = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().gwn_model_bytes(h, ctypes.byref(r), ctypes.byref(q)))
+    return r.value, q.value
+
+
+_WIDTH = {GWN_I_SUMMARY: lambda d: 8, GWN_I_LEAVES: lambda d: 13 if d == 2 else 65, GWN_I_NODES: lambda d: 13,
+          GWN_I_MOMENTS: lambda d: d + d * d + d ** 3, GWN_I_UNCENTERED: lambda d: d + d * d + d ** 3,
+          GWN_I_COMPLEX: lambda d: 18}
+
+
+def gwn_inspect(h, what: int) -> np.ndarray:
+    cnt = ctypes.c_int64()
+    _check(lib().gwn_inspect(h, GWN_I_SUMMARY, None, 0, ctypes.byref(cnt)))
+    summ = np.empty(8)
+    _check(lib().gwn_inspect(h, GWN_I_SUMMARY, _p(summ), 1, ctypes.byref(cnt)))
+    dim = int(summ[0])
+    _check(lib().gwn_inspect(h, what, None, 0, ctypes.byref(cnt)))
+    width = _WIDTH[what](dim)
+    out = np.empty((cnt.value, width))
+    if cnt.value:
+        _check(lib().gwn_inspect(h, what, _p(out), cnt.value, ctypes.byref(cnt)))
+    return out
+
+
+def gwn_profile(enable: bool):
+    """Start (True) or stop (False) traversal-kernel event timing; stopping
+    returns (total_ms, launches)."""
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().gwn_profile(1 if enable else 0, ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def gwn_free(h):
+    if h is not None:
+        _check(lib().gwn_free(h))
+
+
+def gwn_last_error() -> str:
+    return lib().gwn_last_error().decode(errors="replace")
+
+
+class Model:
+    """Owning wrapper of a handle with a torch-facing ``query``."""
+
+    def __init__(self, geometry, params: gwn_params | None = None, **overrides):
+        self.params = params if params is not None else gwn_default_params()
+        for k, v in overrides.items():
+            setattr(self.params, k, v)
+        if hasattr(geometry, "cp_xyz"):
+            self.dim = 3
+            self.h = gwn_build3d(geometry, self.params)
+        else:
+            self.dim = 2
+            self.h = gwn_build2d(geometry, self.params)
+
+    def set(self, **kw):
+        p = gwn_get_params(self.h)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        gwn_set_params(self.h, p)
+        self.params = p
+
+    def query(self, points, out=None, inside=None, stream=None):
+        import torch
+        n = points.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device=points.device)
+        if inside is None:
+            inside = torch.empty(n, dtype=torch.uint8, device=points.device)
+        gwn_query(self.h, points, out, inside, stream)
+        return out, inside
+
+    def counters(self, points, stream=None):
+        import torch
+        c = torch.zeros(GWN_NCOUNTERS, dtype=torch.int64, device=points.device)
+        gwn_query_counters(self.h, points, c, stream)
+        return dict(zip(COUNTER_NAMES, c.cpu().tolist()))
+
+    def bytes(self):
+        return gwn_model_bytes(self.h)
+
+    def inspect(self, what):
+        return gwn_inspect(self.h, what)
+
+    def close(self):
+        if self.h is not None:
+            gwn_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every symbol declared in include/gwn.h,
+and validates its inputs on the host (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_19200_amd import gwn as G
+from paper_2605_19200_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "gwn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gwn_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = G.lib()
+    syms = declared_symbols()
+    assert "gwn_query" in syms and "gwn_build2d" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(G.EXPORTED) == syms
+
+
+def test_default_params():
+    p = G.gwn_default_params()
+    assert p.beta == 2.0 and p.taylor_order == 2 and p.max_diag_frac == 0.1 and p.gl_nodes == 10
+
+
+def host_params(**kw):
+    return G.gwn_default_params(device=-1, **kw)
+
+
+def test_host_only_build_and_query_rejected():
+    curves, q = W.config1()
+    h = G.gwn_build2d(curves, host_params())
+    s = G.gwn_inspect(h, G.GWN_I_SUMMARY)[0]
+    assert s[0] == 2 and s[1] == 64 and s[2] >= 64 and s[3] == 2 * s[2] - 1
+    st = G.lib().gwn_query(h, None, 0, None, None, None)
+    assert st == G.GWN_EINVAL and "host-only" in G.gwn_last_error()
+    G.gwn_free(h)
+
+
+@pytest.mark.parametrize("bad", ["degree", "weight", "nan", "offset", "beta"])
+def test_invalid_inputs(bad):
+    p = [np.array([[0, 0], [1, 0], [1, 1.0]]), np.array([1.0, 0.5, 1.0])]
+    params = host_params()
+    if bad == "weight":
+        p[1] = np.array([1.0, 0.0, 1.0])
+    if bad == "nan":
+        p[0] = np.array([[0, 0], [np.nan, 0], [1, 1.0]])
+    c = W.Curves2D.from_list([tuple(p)])
+    if bad == "degree":
+        c.degree[0] = 4
+    if bad == "offset":
+        c.cp_offset[1] = 2
+    if bad == "beta":
+        params.beta = 1.5
+    with pytest.raises(G.GwnError) as ei:
+        G.gwn_build2d(c, params)
+    assert ei.value.status == G.GWN_EINVAL
+    assert G.gwn_last_error()
+
+
+def test_empty_model():
+    c = W.Curves2D.from_list([])
+    h = G.gwn_build2d(c, host_params())
+    assert G.gwn_inspect(h, G.GWN_I_SUMMARY)[0][2] == 0
+    G.gwn_free(h)
+
+
+def test_set_params_validation():
+    curves, _ = W.config1()
+    h = G.gwn_build2d(curves, host_params())
+    p = G.gwn_get_params(h)
+    p.taylor_order = 9
+    with pytest.raises(G.GwnError):
+        G.gwn_set_params(h, p)
+    p.taylor_order = 1
+    p.beta = 8.0
+    G.gwn_set_params(h, p)
+    assert G.gwn_get_params(h).beta == 8.0 and G.gwn_get_params(h).taylor_order == 1
+    G.gwn_free(h)

@@ -1,0 +1,186 @@
+"""GPU parity of the 2D query path against the CPU oracle (direct FP64 GWN
+summed over every curve).  Every call goes through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2605_19200_amd import gwn as G
+from paper_2605_19200_amd import presets
+from paper_2605_19200_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6          # |w_gpu - w_oracle| bound of the FP64 form
+BAND = 1e-3         # containment must agree where |w_oracle - 0.5| > BAND
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def run(model, q):
+    out, ins = model.query(dev(q))
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ins.cpu().numpy()
+
+
+def check(w, ins, ref, tol=TOL):
+    err = np.abs(w - ref)
+    assert np.all(np.isfinite(w))
+    assert err.max() <= tol, f"max |dw| = {err.max():.3e}"
+    sure = np.abs(ref - 0.5) > BAND
+    assert np.array_equal(ins[sure].astype(bool), (ref >= 0.5)[sure])
+    assert np.array_equal(ins.astype(bool), w >= 0.5)
+
+
+@pytest.fixture(scope="module")
+def cfg1(oracle):
+    curves, q = W.config1()
+    return curves, q, oracle.gwn2d(curves, q)
+
+
+def test_config1_all_direct(cfg1):
+    curves, q, ref = cfg1
+    m = G.Model(curves, presets.params(presets.FP64_2D, beta=1e8))
+    w, ins = run(m, q)
+    check(w, ins, ref, tol=1e-11)
+
+
+@pytest.mark.parametrize("preset", ["FP64_2D", "PAPER_ORDER_2D"])
+def test_config1_fp64_form(cfg1, preset):
+    curves, q, ref = cfg1
+    m = G.Model(curves, presets.params(getattr(presets, preset)))
+    w, ins = run(m, q)
+    check(w, ins, ref)
+
+
+def test_ragged_sizes_bitwise(cfg1):
+    curves, q, ref = cfg1
+    m = G.Model(curves, presets.params(presets.FP64_2D))
+    full, _ = run(m, q)
+    for n in [1, 2, 63, 64, 65, 255, 257, 1000]:
+        w, ins = run(m, q[:n])
+        assert np.array_equal(w, full[:n]), n
+        check(w, ins, ref[:n])
+    out = torch.empty(0, dtype=torch.float64, device="cuda")
+    G.gwn_query(m.h, dev(np.zeros((0, 2))), out, None)
+    torch.cuda.synchronize()
+
+
+def test_degenerate_models(oracle):
+    q = W.Rng(21, "q").uniform((300, 2), -1.5, 1.5)
+    # empty model
+    m = G.Model(W.Curves2D.from_list([]), presets.params(presets.FP64_2D))
+    w, _ = run(m, q)
+    assert np.all(w == 0)
+    # one curve: the root is a leaf
+    one = W.Curves2D.from_list([W.circle_curves((0, 0), 1.0, 3)[0]])
+    m = G.Model(one, presets.params(presets.FP64_2D, beta=1e8))
+    w, ins = run(m, q)
+    check(w, ins, oracle.gwn2d(one, q), tol=1e-12)
+    # straight segments, square corners/edges (direct values 0.25 / 0.5)
+    sq = W.Curves2D.from_list(W.square_trim())
+    qs = np.array([[0, 0], [1, 1], [0.5, 0], [1, 0.3], [0.5, 0.5], [1.5, 0.5]], float)
+    m = G.Model(sq, presets.params(presets.FP64_2D, beta=1e8))
+    w, _ = run(m, qs)
+    assert np.allclose(w, [0.25, 0.25, 0.5, 0.5, 1.0, 0.0], atol=1e-14)
+
+
+def test_circle_boundary_and_near(oracle):
+    circ = W.Curves2D.from_list(W.circle_curves((0.1, 0.2), 0.9, 4))
+    th = W.Rng(22, "th").uniform(200, 0, 2 * math.pi)
+    on = np.stack([0.1 + 0.9 * np.cos(th), 0.2 + 0.9 * np.sin(th)], 1)
+    exact = G.Model(circ, presets.params(presets.FP64_2D, beta=1e8))   # every leaf direct
+    prod = G.Model(circ, presets.params(presets.FP64_2D))
+    for m, tol in [(exact, 1e-12), (prod, TOL)]:
+        w, _ = run(m, on)
+        assert np.abs(w - 0.5).max() < max(tol, 1e-8)
+        for d in [1e-3, 1e-6, 1e-8]:
+            inner = np.stack([0.1 + (0.9 - d) * np.cos(th), 0.2 + (0.9 - d) * np.sin(th)], 1)
+            outer = np.stack([0.1 + (0.9 + d) * np.cos(th), 0.2 + (0.9 + d) * np.sin(th)], 1)
+            wi, _ = run(m, inner)
+            wo, _ = run(m, outer)
+            assert np.abs(wi - 1).max() < tol and np.abs(wo).max() < tol, (d, tol)
+
+
+@pytest.fixture(scope="module")
+def cfg2(oracle):
+    curves, _ = W.config2(grid=4)
+    lo, hi = curves.bbox()
+    small = W.grid_queries(lo, hi, (48, 48))
+    return curves, small, oracle.gwn2d(curves, small)
+
+
+@pytest.mark.parametrize("preset", ["FP64_2D", "PAPER_ORDER_2D"])
+def test_config2_fp64_small_grid(cfg2, preset):
+    curves, q, ref = cfg2
+    m = G.Model(curves, presets.params(getattr(presets, preset)))
+    w, ins = run(m, q)
+    check(w, ins, ref)
+
+
+def test_config2_full_grid_sampled(oracle):
+    curves, q = W.config2()
+    m = G.Model(curves, presets.params(presets.FP64_2D))
+    w, ins = run(m, q)
+    idx = W.Rng(23, "sample").permutation(q.shape[0])[:384]
+    ref = oracle.gwn2d(curves, q[idx])
+    check(w[idx], ins[idx], ref)
+
+
+def test_config2_mixed_form(cfg2):
+    curves, q, ref = cfg2
+    m = G.Model(curves, presets.params(presets.MIXED_2D))
+    w, ins = run(m, q)
+    err = np.abs(w - ref)
+    assert err.max() < 5e-3, err.max()
+    sure = np.abs(ref - 0.5) > BAND
+    assert np.array_equal(ins[sure].astype(bool), (ref >= 0.5)[sure])
+    band = np.abs(w - 0.5) < presets.MIXED_2D["reclass_band"]
+    assert np.abs(w[band] - ref[band]).max(initial=0) <= TOL   # reclassified in FP64
+
+
+def test_batch_bitwise_equals_solo(cfg1, cfg2):
+    c1, q1, _ = cfg1
+    c2, q2, _ = cfg2
+    m1 = G.Model(c1, presets.params(presets.FP64_2D))
+    m2 = G.Model(c2, presets.params(presets.MIXED_2D))
+    s1, _ = run(m1, q1)
+    s2, _ = run(m2, q2)
+    parts = [(m1, q1[:1000]), (m2, q2[:700]), (m1, q1[1000:1001]), (m2, q2[700:])]
+    pts = np.concatenate([p for _, p in parts])
+    off = np.cumsum([0] + [p.shape[0] for _, p in parts])
+    out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+    ins = torch.empty(pts.shape[0], dtype=torch.uint8, device="cuda")
+    G.gwn_query_batch([m.h for m, _ in parts], off, dev(pts), out, ins)
+    torch.cuda.synchronize()
+    w = out.cpu().numpy()
+    assert np.array_equal(w[off[0]:off[1]], s1[:1000])
+    assert np.array_equal(w[off[1]:off[2]], s2[:700])
+    assert np.array_equal(w[off[2]:off[3]], s1[1000:1001])
+    assert np.array_equal(w[off[3]:off[4]], s2[700:])
+
+
+def test_error_decreases_with_order(cfg2):
+    """At a fixed far-field factor the error drops with each added order of
+    the expansion (Sec. 4.2: about an order of magnitude per order)."""
+    curves, q, ref = cfg2
+    m = G.Model(curves, presets.params(presets.FP64_2D, beta=6.0, taylor_order=0))
+    errs = []
+    for order in range(0, 9):
+        m.set(taylor_order=order)
+        w, _ = run(m, q)
+        errs.append(np.abs(w - ref).max())
+    assert errs[0] < 0.5
+    for p in range(8):
+        assert errs[p + 1] < errs[p], errs
+
+
+def test_counters(cfg1):
+    curves, q, _ = cfg1
+    m = G.Model(curves, presets.params(presets.FP64_2D))
+    c = m.counters(dev(q))
+    assert c["leaves"] > 0 and c["nodes"] > 0 and c["overflow"] == 0
+    assert c["leaf_fast"] <= c["leaves"] and c["angles"] >= c["leaf_fast"]

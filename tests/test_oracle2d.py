@@ -170,6 +170,18 @@ def test_dense_bruteforce_near_field(oracle):
         assert np.abs(got - ref).max() < 1e-11
 
 
+def test_hairpin_curve_against_dense(oracle):
+    """A sharply turning quadratic from the SVG-like drawing, with q inside its
+    hull but away from the turn: the angle integrand has a feature far from
+    the closest point that a coarse adaptive start can miss."""
+    p = np.array([[0.38020299, 0.93432087], [0.26739145, 0.95485183], [0.37813275, 0.92541035]])
+    wt = np.array([0.62127915, 1.23228282, 0.94014809])
+    q = np.array([0.34729583, 0.93765536])
+    C = W.Curves2D.from_list([(p, wt)])
+    ref = _dense_angle(p, wt, q, panels=20000)
+    assert abs(oracle.gwn2d(C, q[None])[0] - ref) < 1e-12
+
+
 def test_orientation_elevation_reweighting_subdivision(oracle):
     curves, q = W.config1()
     curves = curves.subset(range(0, 20))
