@@ -131,6 +131,25 @@ __device__ __forceinline__ double chord_angle(double ax, double ay, double bx, d
     return atan2(cr, dt);
 }
 
+// Sum of the chord angles seen from q (direct leaf contributions).
+// (Measured on gfx950: one FP64 atan2 per chord is cheaper than carrying a
+// rescaled complex product of the chords and recovering the 2 pi multiple
+// from a coarse FP32 sum.)
+struct AngleAcc {
+    double sum;
+    double extra;       // terminal-piece angles
+};
+
+__device__ __forceinline__ void angle_init(AngleAcc &A) { A.sum = 0.0; A.extra = 0.0; }
+
+__device__ __forceinline__ void angle_add_chord(AngleAcc &A, double cr, double dt)
+{
+    if (cr == 0.0 && dt <= 0.0) return;   // q on the chord or at an end point
+    A.sum += atan2(cr, dt);
+}
+
+__device__ __forceinline__ double angle_total(const AngleAcc &A) { return A.sum + A.extra; }
+
 __device__ __forceinline__ double lerp_exact(double a, double b, double t, double s)
 {
     return fma(t, b, s * a);   // exact at t = 0 and t = 1
@@ -149,8 +168,8 @@ __device__ __forceinline__ double lerp_exact(double a, double b, double t, doubl
 // The end point of each piece is carried to the next so consecutive chords
 // share their end points bit for bit.
 template <bool COUNT>
-__device__ double leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__ prims, double qx, double qy,
-                         double eps_on, Ctr &ctr, bool &overflow)
+__device__ void leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__ prims, double qx, double qy,
+                       double eps_on, AngleAcc &A, Ctr &ctr, bool &overflow)
 {
     const int leaf = -1 - nd->right;
     const Prim2 *P = prims + leaf;
@@ -165,20 +184,20 @@ __device__ double leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__
     const bool outside = qx < nd->m[0] || qy < nd->m[1] || qx > nd->m[2] || qy > nd->m[3];
     if (outside || nd->degree == 1) {
         if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
-        return chord_angle(bx[0], by[0], bx[3], by[3]);
+        angle_add_chord(A, bx[0] * by[3] - by[0] * bx[3], bx[0] * bx[3] + by[0] * by[3]);
+        return;
     }
-    if (!(fabs(qx) < INFINITY && fabs(qy) < INFINITY)) return NAN;
+    if (!(fabs(qx) < INFINITY && fabs(qy) < INFINITY)) { A.extra = NAN; return; }
     // On-boundary rule: a piece whose control points all lie within eps_on
     // of q (|x_i| / w_i < eps_on with w_i >= the leaf's smallest weight) is
     // terminal.
     const double wmin = fmin(fmin(P->h[2], P->h[5]), fmin(P->h[8], P->h[11]));
     const double on_tol = eps_on * wmin;
-    double sum = 0.0;
     int level = 1;
     uint64_t k = 0;
     double p0x = bx[0], p0y = by[0];
     for (int it = 0;; ++it) {
-        if (it >= kMaxBisectIter) { overflow = true; return NAN; }
+        if (it >= kMaxBisectIter) { overflow = true; A.extra = NAN; return; }
         const double inv = ldexp(1.0, -level);
         const double t0 = (double)k * inv, t1 = (double)(k + 1) * inv;
         const double s0 = 1.0 - t0, s1 = 1.0 - t1;
@@ -218,24 +237,25 @@ __device__ double leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__
             k <<= 1;
             continue;
         }
-        {
-            // Outside: the chord angle is exact.  Terminal piece still holding
-            // q (within eps_on, or at the depth limit): q is on the curve to
-            // tolerance, and the piece takes the mean of its two one-sided
-            // limits, i.e. its chord angle with the jump of +-pi removed
-            // when q lies between its end points.
+        if (out) {
+            // outside: the chord angle is exact
+            angle_add_chord(A, p0x * p3y - p0y * p3x, p0x * p3x + p0y * p3y);
+        } else {
+            // Terminal piece still holding q (within eps_on, or at the depth
+            // limit): q is on the curve to tolerance, and the piece takes the
+            // mean of its two one-sided limits, i.e. its chord angle with the
+            // jump of +-pi removed when q lies between its end points.
             double a = chord_angle(p0x, p0y, p3x, p3y);
-            if (!out && fabs(a) > 0.5 * kPi) a -= copysign(kPi, a);
-            sum += a;
-            if (COUNT) ctr.v[GWN_C_ANGLES]++;
+            if (fabs(a) > 0.5 * kPi) a -= copysign(kPi, a);
+            A.extra += a;
         }
+        if (COUNT) ctr.v[GWN_C_ANGLES]++;
         p0x = p3x;
         p0y = p3y;
         while (level > 0 && (k & 1)) { k >>= 1; --level; }
         if (level == 0) break;
         ++k;
     }
-    return sum;
 }
 
 // Far-field contribution of an accepted 2D cluster, as an angle in radians.
@@ -275,7 +295,9 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     const float qxf = (float)qx, qyf = (float)qy;
     const double beta2 = F32 ? M.beta2_mixed : M.beta2;
     const float beta2f = (float)M.beta2_mixed;
-    double acc = 0.0;
+    double acc = 0.0;      // far-field terms, in radians
+    AngleAcc A;            // direct (chord) angles
+    angle_init(A);
     int cur = 0;
     uint64_t curmask = mask;
     int sp = 0;
@@ -285,7 +307,7 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
         const int right = nd->right;
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            if (active) acc += leaf2d<COUNT>(nd, prims, qx, qy, M.eps_on, ctr, overflow);
+            if (active) leaf2d<COUNT>(nd, prims, qx, qy, M.eps_on, A, ctr, overflow);
         } else {
             bool far = false;
             if (active) {
@@ -320,7 +342,7 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
         curmask = uniform_u64(S.mask[w][sp]);
     }
     (void)me;
-    return acc * (1.0 / (2.0 * kPi));
+    return (angle_total(A) + acc) * (1.0 / (2.0 * kPi));
 }
 
 template <bool COUNT>
@@ -336,13 +358,12 @@ __device__ __forceinline__ void flush_counters(Ctr &ctr, long long *counters)
 }
 
 // Main query kernel (2D): one wave per 64 consecutive sorted queries of one
-// segment.  Mixed-precision segments run the FP32 far-field pass and append
-// queries with |w - 0.5| < band to the reclassification list.
+// segment.  Mixed-precision segments run the FP32 far-field pass and then
+// re-evaluate in FP64 the lanes with |w - 0.5| < band.
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double *__restrict__ pts,
                                                     const int32_t *__restrict__ perm, double *__restrict__ out_w,
-                                                    uint8_t *__restrict__ out_in, int32_t *__restrict__ reclass,
-                                                    int32_t *__restrict__ reclass_n, long long *counters)
+                                                    uint8_t *__restrict__ out_in, long long *counters)
 {
     __shared__ StackLDS S;
     const int w = threadIdx.x >> 6;
@@ -371,64 +392,26 @@ __global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double 
     bool overflow = false;
     double wq;
     const bool mixed = M.precision == GWN_MIXED;
-    if (mixed) wq = traverse2d<true, COUNT>(M, qx, qy, mask, S, w, ctr, overflow);
-    else wq = traverse2d<false, COUNT>(M, qx, qy, mask, S, w, ctr, overflow);
+    if (mixed) {
+        // FP32 far-field pass, then the FP64 form for the lanes of this wave
+        // whose value lies within the band around 0.5 (Morton neighbours, so
+        // the FP64 traversal of the subset stays coherent).
+        wq = traverse2d<true, COUNT>(M, qx, qy, mask, S, w, ctr, overflow);
+        const bool need = valid && fabs(wq - 0.5) < M.band;
+        const uint64_t rmask = __ballot(need);
+        if (rmask) {
+            const double r = traverse2d<false, COUNT>(M, qx, qy, rmask, S, w, ctr, overflow);
+            if (need) wq = r;
+            if (COUNT && need) ctr.v[GWN_C_RECLASS]++;
+        }
+    } else {
+        wq = traverse2d<false, COUNT>(M, qx, qy, mask, S, w, ctr, overflow);
+    }
     if (valid) {
         if (overflow) {
             wq = NAN;
             atomicOr(M.flag, 1);
             if (COUNT) ctr.v[GWN_C_OVERFLOW]++;
-        }
-        if (mixed && fabs(wq - 0.5) < M.band) {
-            if (COUNT) ctr.v[GWN_C_RECLASS]++;
-            if (reclass) reclass[atomicAdd(reclass_n, 1)] = row;
-        }
-        if (out_w) out_w[row] = wq;
-        if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
-    }
-    flush_counters<COUNT>(ctr, counters);
-}
-
-// FP64 re-evaluation of the reclassification list (mixed form).  Lanes of a
-// wave may belong to different models; each distinct model is traversed in
-// turn with the mask of its lanes.
-template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_reclass2d(LaunchTable T, const double *__restrict__ pts,
-                                                      const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ list_n, double *__restrict__ out_w,
-                                                      uint8_t *__restrict__ out_in, long long *counters)
-{
-    __shared__ StackLDS S;
-    const int w = threadIdx.x >> 6;
-    const int lane = lane_id();
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int count = *list_n;
-    if ((int64_t)blockIdx.x * kBlock + w * 64 >= count) return;
-    const bool valid = i < count;
-    const int row = valid ? list[i] : 0;
-    const int seg = valid ? find_seg(T, row) : 0;
-    const double qx = valid ? pts[2 * (int64_t)row] : 0.0;
-    const double qy = valid ? pts[2 * (int64_t)row + 1] : 0.0;
-    Ctr ctr;
-#pragma unroll
-    for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
-    bool overflow = false;
-    double wq = 0.0;
-    uint64_t todo = __ballot(valid);
-    while (todo) {
-        const int leader = __builtin_ctzll(todo);
-        const int mseg = __shfl(seg, leader);
-        const int model = uniform_i(T.seg_model[mseg]);
-        const uint64_t mine = __ballot(valid && T.seg_model[seg] == model) & todo;
-        const DevModel &M = T.models[model];
-        double r = traverse2d<false, COUNT>(M, qx, qy, mine, S, w, ctr, overflow);
-        if ((mine >> lane) & 1) wq = r;
-        todo &= ~mine;
-    }
-    if (valid) {
-        if (overflow) {
-            wq = NAN;
-            atomicOr(T.models[T.seg_model[seg]].flag, 1);
         }
         if (out_w) out_w[row] = wq;
         if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
@@ -565,20 +548,11 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
             const int grid_w = (T.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
             if (counters)
                 hipLaunchKernelGGL(k_query2d<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
-                                   any_mixed ? list : nullptr, list_n, (long long *)counters);
+                                   (long long *)counters);
             else
                 hipLaunchKernelGGL(k_query2d<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
-                                   any_mixed ? list : nullptr, list_n, nullptr);
+                                   nullptr);
             e = hipGetLastError();
-            if (e == hipSuccess && any_mixed) {
-                if (counters)
-                    hipLaunchKernelGGL(k_reclass2d<true>, dim3(grid_q), dim3(kBlock), 0, stream, T, pts, list, list_n,
-                                       ow, oi, (long long *)counters);
-                else
-                    hipLaunchKernelGGL(k_reclass2d<false>, dim3(grid_q), dim3(kBlock), 0, stream, T, pts, list,
-                                       list_n, ow, oi, nullptr);
-                e = hipGetLastError();
-            }
             if (e != hipSuccess) st = hip_err(e, "query launch", err);
         } else {
             st = launch_query3d(T, pts, v_out, ow, oi, any_mixed ? list : nullptr, list_n, (long long *)counters,
