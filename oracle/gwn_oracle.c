@@ -105,10 +105,11 @@ static double gl_panel(fn1 f, void *ctx, double a, double b)
 
 /* Adaptive Gauss-Legendre on [a, b]: a panel is accepted when it agrees
  * with the sum over its two halves to within its share (proportional to its
- * length) of the tolerance, or to 1e-15 relative.  Work is bounded: at most
+ * length) of the tolerance, or to `rel` relative (the roundoff level of the
+ * integrand near a near-singular peak: forming H - q W loses ~|H|/|A| digits).  Work is bounded: at most
  * MAX_SPLITS bisections and a bisection depth of MAX_DEPTH per call. */
 #define MAX_SPLITS 2000
-static double adapt(fn1 f, void *ctx, double a, double b, double tol)
+static double adapt(fn1 f, void *ctx, double a, double b, double tol, double rel)
 {
     if (!(b > a)) return 0.0;
     double sa[MAX_DEPTH + 2], sb[MAX_DEPTH + 2], sw[MAX_DEPTH + 2];
@@ -122,7 +123,7 @@ static double adapt(fn1 f, void *ctx, double a, double b, double tol)
         double l = gl_panel(f, ctx, pa, m), r = gl_panel(f, ctx, m, pb);
         double err = fabs(l + r - whole);
         double loc = tol * (pb - pa) / (b - a);
-        if (err <= loc || err <= 1e-15 * fabs(l + r) || sp >= MAX_DEPTH || splits >= MAX_SPLITS ||
+        if (err <= loc || err <= rel * fabs(l + r) || sp >= MAX_DEPTH || splits >= MAX_SPLITS ||
             !(m > pa && m < pb)) {
             total += l + r;
         } else {
@@ -145,8 +146,10 @@ static int cmp_dbl(const void *x, const void *y)
 #define MAX_BREAKS 1024
 #define UNIFORM_2D 64   /* initial uniform panels, 2D angle integral */
 #define UNIFORM_3D 2    /* initial uniform panels, each 3D level */
+#define REL_2D 1e-12    /* relative acceptance floor of a panel, 2D */
+#define REL_3D 1e-10    /* relative acceptance floor of a panel, 3D */
 static double graded(fn1 f, void *ctx, double a, double b, const double *centres,
-                     const double *h0, int nc, double tol, int uniform)
+                     const double *h0, int nc, double tol, int uniform, double rel)
 {
     double br[MAX_BREAKS];
     int nb = 0;
@@ -170,22 +173,24 @@ static double graded(fn1 f, void *ctx, double a, double b, const double *centres
     qsort(br, nb, sizeof(double), cmp_dbl);
     double s = 0.0;
     for (int i = 0; i + 1 < nb; ++i)
-        if (br[i + 1] > br[i]) s += adapt(f, ctx, br[i], br[i + 1], tol);
+        if (br[i + 1] > br[i]) s += adapt(f, ctx, br[i], br[i + 1], tol, rel);
     return s;
 }
 
-/* Bernstein basis of degree n (<= 3) and its derivative, plain formulas. */
+/* Bernstein basis of degree n (<= 3) and its derivative, plain formulas
+ * B_i = C(n,i) t^i (1-t)^(n-i), B_i' = n (B^{n-1}_{i-1} - B^{n-1}_i). */
 static void bernstein(int n, double t, double *B, double *dB)
 {
     static const double binom[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
     double s = 1.0 - t;
+    double tp[4] = {1.0, t, t * t, t * t * t}, sp[4] = {1.0, s, s * s, s * s * s};
     for (int i = 0; i <= n; ++i) {
-        B[i] = binom[n][i] * pow(t, i) * pow(s, n - i);
+        B[i] = binom[n][i] * tp[i] * sp[n - i];
         if (dB) {
             double d = 0.0;
-            if (i > 0) d += i * pow(t, i - 1) * pow(s, n - i);
-            if (i < n) d -= (n - i) * pow(t, i) * pow(s, n - i - 1);
-            dB[i] = binom[n][i] * d;
+            if (i > 0) d += binom[n - 1][i - 1] * tp[i - 1] * sp[n - i];
+            if (i < n) d -= binom[n - 1][i] * tp[i] * sp[n - 1 - i];
+            dB[i] = n * d;
         }
     }
 }
@@ -355,7 +360,9 @@ static double gwn_curve(const curve2 *c, double eps_on)
     if (d < eps_on && speed > 0.0) return gwn_curve_onboundary(c, sx, sy, eps_on);
     double h0 = fmax(d, eps_on) / speed;
     if (!(h0 > 0.0)) h0 = 1e-16;
-    return graded(dtheta, (void *)c, 0.0, 1.0, &ts, &h0, 1, 1e-14, UNIFORM_2D);
+    double size = hypot(xmx - xmn, ymx - ymn);
+    double rel = fmax(REL_2D, 64.0 * 2.220446049250313e-16 * size / fmax(d, eps_on));
+    return graded(dtheta, (void *)c, 0.0, 1.0, &ts, &h0, 1, 1e-14, UNIFORM_2D, rel);
 }
 
 /*
@@ -511,11 +518,14 @@ static void foot_point(const patch3 *p, double *us, double *vs)
 
 typedef struct {
     const patch3 *p;
+    int far;              /* q separated from the patch: no grading needed */
     double v;             /* inner integration at fixed v */
     int n;                /* trim curve degree */
     double U[3], V[3], Wt[3]; /* homogeneous trim control points */
     double us, vs, d, su, sv; /* foot point, its distance, |S_u|, |S_v| there */
     double eps_on;
+    double rel;           /* relative acceptance floor (integrand noise level) */
+    double diag;          /* control-point box diagonal */
 } green_ctx;
 
 static double inner_g(double s, void *ctx)
@@ -530,13 +540,14 @@ static double F_inner(green_ctx *g, double u, double v)
 {
     if (!(u > 0.0)) return 0.0;
     g->v = v;
+    if (g->far) return adapt(inner_g, g, 0.0, u, 1e-15, g->rel);
     double c = fmin(fmax(g->us, 0.0), u);
     double S[3];
     patch_point(g->p, c, v, S, NULL, NULL);
     double dx = S[0] - g->p->q[0], dy = S[1] - g->p->q[1], dz = S[2] - g->p->q[2];
     double dist = sqrt(dx * dx + dy * dy + dz * dz);
     double h0 = fmax(dist, g->eps_on) / (g->su + 1e-300);
-    return graded(inner_g, g, 0.0, u, &c, &h0, 1, 1e-15, UNIFORM_3D);
+    return graded(inner_g, g, 0.0, u, &c, &h0, 1, 1e-15, UNIFORM_3D, g->rel);
 }
 
 static void trim_eval(const green_ctx *g, double t, double *u, double *v, double *du, double *dv)
@@ -570,6 +581,7 @@ static double outer_f(double t, void *ctx)
  * curve crosses v = v* and toward its point nearest (u*, v*). */
 static double trim_contribution(green_ctx *g)
 {
+    if (g->far) return adapt(outer_f, g, 0.0, 1.0, 1e-14, g->rel);
     double centres[8], h0[8];
     int nc = 0;
     const int S = 64;
@@ -594,17 +606,40 @@ static double trim_contribution(green_ctx *g)
         prev_f = f;
         prev_t = t;
     }
+    const int n_cross = nc;
     centres[nc++] = best_t;
     for (int k = 0; k < nc; ++k) {
         double u, v, du, dv, S3[3], Su[3], Sv[3];
         trim_eval(g, centres[k], &u, &v, &du, &dv);
+        if (k < n_cross) {
+            /* crossing of v = v*: F(u, v) has a peak of width ~ d / |S_v|
+             * in v there (d = distance from q to the surface) */
+            h0[k] = fmax(g->d, g->eps_on) / (g->sv * fabs(dv) + 1e-300);
+            continue;
+        }
         patch_point(g->p, fmin(fmax(u, 0), 1), fmin(fmax(v, 0), 1), S3, Su, Sv);
         double dx = S3[0] - g->p->q[0], dy = S3[1] - g->p->q[1], dz = S3[2] - g->p->q[2];
         double dist = sqrt(dx * dx + dy * dy + dz * dz);
         double speed = g->su * fabs(du) + g->sv * fabs(dv);
         h0[k] = fmax(dist, g->eps_on) / (speed + 1e-300);
     }
-    return graded(outer_f, g, 0.0, 1.0, centres, h0, nc, 1e-14, UNIFORM_3D);
+    return graded(outer_f, g, 0.0, 1.0, centres, h0, nc, 1e-14, UNIFORM_3D, g->rel);
+}
+
+static double gwn_patch(const patch3 *p, int n_trim, const int32_t *tdeg, const int64_t *tcoff,
+                        const double *tuv, const double *tw, double eps_on);
+
+/* On the surface: the mean of the two one-sided limits, approximated by the
+ * mean of the values at q +- delta n (n the unit normal at the foot point,
+ * delta = 1e3 eps_on). */
+static double gwn_patch_onsurface(const patch3 *p, const double nrm[3], int n_trim, const int32_t *tdeg,
+                                  const int64_t *tcoff, const double *tuv, const double *tw, double eps_on)
+{
+    patch3 a = *p, b = *p;
+    double delta = 1e3 * eps_on;
+    for (int k = 0; k < 3; ++k) { a.q[k] += delta * nrm[k]; b.q[k] -= delta * nrm[k]; }
+    return 0.5 * (gwn_patch(&a, n_trim, tdeg, tcoff, tuv, tw, eps_on) +
+                  gwn_patch(&b, n_trim, tdeg, tcoff, tuv, tw, eps_on));
 }
 
 static double gwn_patch(const patch3 *p, int n_trim, const int32_t *tdeg, const int64_t *tcoff,
@@ -614,14 +649,75 @@ static double gwn_patch(const patch3 *p, int n_trim, const int32_t *tdeg, const 
     memset(&g, 0, sizeof g);
     g.p = p;
     g.eps_on = eps_on;
-    foot_point(p, &g.us, &g.vs);
+    /* well separated (distance to the control-point box at least its
+     * diagonal): the integrand is smooth, plain adaptive quadrature */
     {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                for (int k = 0; k < 3; ++k) {
+                    double x = p->H[a][b][k] / p->H[a][b][3];
+                    lo[k] = fmin(lo[k], x);
+                    hi[k] = fmax(hi[k], x);
+                }
+        double d2 = 0, diag2 = 0;
+        for (int k = 0; k < 3; ++k) {
+            double e = fmax(fmax(lo[k] - p->q[k], p->q[k] - hi[k]), 0.0);
+            d2 += e * e;
+            diag2 += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+        }
+        g.far = d2 >= diag2;
+        g.rel = REL_3D;
+        g.diag = sqrt(diag2);
+    }
+    if (!g.far) foot_point(p, &g.us, &g.vs);
+    if (!g.far) {
         double S[3], Su[3], Sv[3];
         patch_point(p, g.us, g.vs, S, Su, Sv);
         g.su = sqrt(Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2]);
         g.sv = sqrt(Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2]);
         if (!(g.su > 0)) g.su = 1e-12;
         if (!(g.sv > 0)) g.sv = 1e-12;
+        double dx = S[0] - p->q[0], dy = S[1] - p->q[1], dz = S[2] - p->q[2];
+        g.d = sqrt(dx * dx + dy * dy + dz * dz);
+        /* near the foot point A = H - q W carries absolute roundoff
+         * ~eps |H|, i.e. relative noise ~eps diag / d */
+        g.rel = fmax(REL_3D, 64.0 * 2.220446049250313e-16 * g.diag / fmax(g.d, eps_on));
+        double n[3] = {Su[1] * Sv[2] - Su[2] * Sv[1], Su[2] * Sv[0] - Su[0] * Sv[2], Su[0] * Sv[1] - Su[1] * Sv[0]};
+        double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (sqrt(dx * dx + dy * dy + dz * dz) < eps_on && nn > 0.0) {
+            /* inside the visible region only: q on the trimmed-away part is not
+             * on this surface; the interior test uses the trim loops' winding */
+            int visible = 1;
+            if (n_trim > 0) {
+                double wsum = 0.0;
+                for (int cc = 0; cc < n_trim; ++cc) {
+                    /* angle subtended at (u*, v*) by the trim polygon of each curve,
+                     * sampled finely: a crude but sufficient inside test */
+                    int nd = tdeg[cc];
+                    double U[3], V[3], Wt[3];
+                    for (int j = 0; j <= nd; ++j) {
+                        int64_t o = tcoff[cc] + j;
+                        Wt[j] = tw[o]; U[j] = tuv[2 * o] * tw[o]; V[j] = tuv[2 * o + 1] * tw[o];
+                    }
+                    double pu = 0, pv = 0;
+                    for (int s = 0; s <= 64; ++s) {
+                        double B[3], t = s / 64.0;
+                        bernstein(nd, t, B, NULL);
+                        double hu = 0, hv = 0, hw = 0;
+                        for (int j = 0; j <= nd; ++j) { hu += B[j] * U[j]; hv += B[j] * V[j]; hw += B[j] * Wt[j]; }
+                        double cu = hu / hw - g.us, cv = hv / hw - g.vs;
+                        if (s > 0) wsum += atan2(pu * cv - pv * cu, pu * cu + pv * cv);
+                        pu = cu; pv = cv;
+                    }
+                }
+                visible = fabs(wsum) > PI_;
+            }
+            if (visible) {
+                for (int k = 0; k < 3; ++k) n[k] /= nn;
+                return gwn_patch_onsurface(p, n, n_trim, tdeg, tcoff, tuv, tw, eps_on);
+            }
+        }
     }
     double total = 0.0;
     if (n_trim == 0) {
