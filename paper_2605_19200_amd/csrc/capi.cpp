@@ -407,7 +407,7 @@ extern "C" gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *
     if (!h) return fail(GWN_EINVAL, "NULL handle");
     if (resident) *resident = h->m.arena_bytes + 256;
     // keys + sort double buffer + permutation + reclass list + sort temp
-    if (per_query) *per_query = 8 + 8 + 4 + 4 + 4 + 16;
+    if (per_query) *per_query = 8 + 8 + 4 + 4 + 16;   // keys x2, perm x2, sort temp
     return GWN_OK;
 }
 

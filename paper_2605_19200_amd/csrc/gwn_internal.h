@@ -2,6 +2,7 @@
 // and the launch interface between the host build and the HIP kernels.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -55,7 +56,9 @@ struct Prim2 {
 //             the monomials s0^3, s1^3, s2^3, s0^2 s1, s0^2 s2, s1^2 s0,
 //             s1^2 s2, s2^2 s0, s2^2 s1, s0 s1 s2
 // Leaf: t[0..5] = AABB lo[3], hi[3]; `aux` = first index of the leaf's
-// precomputed quadrature nodes, `count` = their number, `right` = -1 - leaf.
+// precomputed quadrature nodes, `count` = their number, t[6..8] = the node
+// counts of the three rules of kLeafRules stored one after the other,
+// `right` = -1 - leaf.
 struct alignas(128) Node3 {
     double c[3];
     double r2;
@@ -85,6 +88,12 @@ struct Trim3 {
     double h[9];          // (w u, w v, w) x 3
     double pad;
 };
+
+// Gauss-Legendre orders of a 3D leaf's direct rules for well-separated
+// queries, finest first, with the distance/half-diagonal ratios from which
+// each is used (error ~ rho^-2n, rho = r + sqrt(r^2 + 1), <= ~3e-9).
+constexpr int kLeafRules[3] = {12, 8, 6};
+constexpr double kLeafRuleRatio[3] = {0.0, 2.5, 6.0};
 
 // Precomputed far-rule quadrature node of a 3D leaf: position and weighted
 // normal (Green-scattered Gauss-Legendre node, Sec. 3.1).
@@ -171,6 +180,7 @@ struct Model {
     std::vector<int32_t> leaf_trim_begin, leaf_trim_count;
     std::vector<QNode3> qnodes;
     std::vector<int64_t> leaf_q_begin, leaf_q_count;
+    std::vector<std::array<int, 3>> leaf_q_rules;
     // device
     int device = -1;
     void *d_arena = nullptr;

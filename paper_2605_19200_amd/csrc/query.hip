@@ -23,35 +23,9 @@
 #include <vector>
 
 #include "gwn_internal.h"
+#include "query_common.h"
 
 namespace gwn {
-
-constexpr int kMaxSeg = 32;
-constexpr int kMaxModels = 8;
-constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kMaxBisectIter = 16384;
-
-struct LaunchTable {
-    int32_t n_seg;
-    int32_t n_waves;
-    int32_t seg_model[kMaxSeg];
-    int32_t woff[kMaxSeg + 1];
-    int64_t qoff[kMaxSeg + 1];
-    DevModel models[kMaxModels];
-};
-
-struct Ctr {
-    long long v[GWN_NCOUNTERS];
-};
-
-__device__ __forceinline__ int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // ---------------------------------------------------------------------------
 // space-filling-curve keys
@@ -277,11 +251,6 @@ __device__ __forceinline__ T taylor2d(T dx, T dy, T d2, const T *m, int order)
     return -(ur * ti + ui * tr);   // -Im(u * t)
 }
 
-struct StackLDS {
-    int node[kWavesPerBlock][kStackDepth];
-    unsigned long long mask[kWavesPerBlock][kStackDepth];
-};
-
 // Traversal of one wave over a 2D model.  `mask`: lanes taking part (wave
 // uniform).  F32: far-field tests and Taylor terms in FP32 (mixed form).
 template <bool F32, bool COUNT>
@@ -343,18 +312,6 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     }
     (void)me;
     return (angle_total(A) + acc) * (1.0 / (2.0 * kPi));
-}
-
-template <bool COUNT>
-__device__ __forceinline__ void flush_counters(Ctr &ctr, long long *counters)
-{
-    if (!COUNT) return;
-#pragma unroll
-    for (int k = 0; k < GWN_NCOUNTERS; ++k) {
-        long long v = ctr.v[k];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane_id() == 0 && v) atomicAdd((unsigned long long *)&counters[k], (unsigned long long)v);
-    }
 }
 
 // Main query kernel (2D): one wave per 64 consecutive sorted queries of one
@@ -421,8 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double 
 
 // 3D kernels live in query3d.hip
 gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t *perm, double *out_w,
-                          uint8_t *out_in, int32_t *reclass, int32_t *reclass_n, long long *counters,
-                          bool any_mixed, hipStream_t stream, std::string &err);
+                          uint8_t *out_in, long long *counters, hipStream_t stream, std::string &err);
 
 // ---------------------------------------------------------------------------
 // host launcher
@@ -487,7 +443,6 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     const int64_t row0 = segs[s0].q_begin;
     int64_t q = 0;
     int32_t wv = 0;
-    bool any_mixed = false;
     for (size_t k = s0; k < s1; ++k) {
         const Model *m = segs[k].model;
         int mi = -1;
@@ -498,7 +453,6 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
             models.push_back(m);
             T.models[mi] = m->dev;
         }
-        any_mixed |= m->params.precision == GWN_MIXED;
         const int j = (int)(k - s0);
         T.seg_model[j] = mi;
         T.qoff[j] = q;
@@ -516,22 +470,20 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     double *ow = out_gwn ? out_gwn + row0 : nullptr;
     uint8_t *oi = out_inside ? out_inside + row0 : nullptr;
 
-    // scratch: keys[2n] (u64), vals[2n] (i32), reclass list [n] + count, sort temp
+    // scratch: keys[2n] (u64), vals[2n] (i32), sort temp
     size_t temp_bytes = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
                                                       (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 54, stream);
     if (e != hipSuccess) return hip_err(e, "radix sort sizing", err);
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t b_keys = al(sizeof(uint64_t) * n), b_vals = al(sizeof(int32_t) * n);
-    const size_t total = 2 * b_keys + 2 * b_vals + b_vals + 256 + al(temp_bytes);
+    const size_t total = 2 * b_keys + 2 * b_vals + al(temp_bytes);
     char *scratch = nullptr;
     e = hipMallocAsync((void **)&scratch, total, stream);
     if (e != hipSuccess) return hip_err(e, "hipMallocAsync scratch", err);
     uint64_t *k_in = (uint64_t *)scratch, *k_out = (uint64_t *)(scratch + b_keys);
     int32_t *v_in = (int32_t *)(scratch + 2 * b_keys), *v_out = (int32_t *)(scratch + 2 * b_keys + b_vals);
-    int32_t *list = (int32_t *)(scratch + 2 * b_keys + 2 * b_vals);
-    int32_t *list_n = (int32_t *)(scratch + 2 * b_keys + 3 * b_vals);
-    void *temp = scratch + 2 * b_keys + 3 * b_vals + 256;
+    void *temp = scratch + 2 * b_keys + 2 * b_vals;
 
     const int grid_q = (int)((n + kBlock - 1) / kBlock);
     gwn_status st = GWN_OK;
@@ -539,7 +491,6 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     e = hipGetLastError();
     if (e == hipSuccess)
         e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k_in, k_out, v_in, v_out, (int)n, 0, 54, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(list_n, 0, sizeof(int32_t), stream);
     if (e != hipSuccess) st = hip_err(e, "key/sort launch", err);
     if (!st) {
         hipEvent_t ev0;
@@ -555,8 +506,7 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
             e = hipGetLastError();
             if (e != hipSuccess) st = hip_err(e, "query launch", err);
         } else {
-            st = launch_query3d(T, pts, v_out, ow, oi, any_mixed ? list : nullptr, list_n, (long long *)counters,
-                                any_mixed, stream, err);
+            st = launch_query3d(T, pts, v_out, ow, oi, (long long *)counters, stream, err);
         }
         prof_end(stream, ev0);
     }

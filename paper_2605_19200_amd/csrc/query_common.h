@@ -1,0 +1,54 @@
+// Launch structures shared by the 2D and 3D query kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gwn_internal.h"
+
+namespace gwn {
+
+constexpr int kMaxSeg = 32;
+constexpr int kMaxModels = 8;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kMaxBisectIter = 16384;
+
+struct LaunchTable {
+    int32_t n_seg;
+    int32_t n_waves;
+    int32_t seg_model[kMaxSeg];
+    int32_t woff[kMaxSeg + 1];
+    int64_t qoff[kMaxSeg + 1];
+    DevModel models[kMaxModels];
+};
+
+struct Ctr {
+    long long v[GWN_NCOUNTERS];
+};
+
+__device__ __forceinline__ int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+struct StackLDS {
+    int node[kWavesPerBlock][kStackDepth];
+    unsigned long long mask[kWavesPerBlock][kStackDepth];
+};
+
+template <bool COUNT>
+__device__ __forceinline__ void flush_counters(Ctr &ctr, long long *counters)
+{
+    if (!COUNT) return;
+#pragma unroll
+    for (int k = 0; k < GWN_NCOUNTERS; ++k) {
+        long long v = ctr.v[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane_id() == 0 && v) atomicAdd((unsigned long long *)&counters[k], (unsigned long long)v);
+    }
+}
+
+}  // namespace gwn

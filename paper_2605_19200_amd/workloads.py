@@ -540,48 +540,69 @@ def cad_assembly(seed=4, n_bodies=39, box=12.0, holes=(1, 3), hole_r=(0.05, 0.15
     return Patches3D.from_list(patches)
 
 
-def near_surface_queries(P: Patches3D, rng: Rng, n, t_max=1e-2):
+def _eval_batch(cps, ws, u, v):
+    """Vectorised eval_patch over (patch control nets, u, v) triples."""
+    h = np.concatenate([cps * ws[..., None], ws[..., None]], axis=-1)      # m,4,4,4
+
+    def bern(t):
+        s = 1 - t
+        return np.stack([s ** 3, 3 * s * s * t, 3 * s * t * t, t ** 3], -1)
+
+    def dbern(t):
+        s = 1 - t
+        return np.stack([-3 * s * s, 3 * s * s - 6 * s * t, 6 * s * t - 3 * t * t, 3 * t * t], -1)
+    bu, bv, du, dv = bern(u), bern(v), dbern(u), dbern(v)
+    H = np.einsum("mi,mj,mijk->mk", bu, bv, h)
+    Hu = np.einsum("mi,mj,mijk->mk", du, bv, h)
+    Hv = np.einsum("mi,mj,mijk->mk", bu, dv, h)
+    W = H[:, 3:4]
+    S = H[:, :3] / W
+    Su = (Hu[:, :3] * W - H[:, :3] * Hu[:, 3:4]) / (W * W)
+    Sv = (Hv[:, :3] * W - H[:, :3] * Hv[:, 3:4]) / (W * W)
+    n = np.cross(Su, Sv)
+    nn = np.linalg.norm(n, axis=1, keepdims=True)
+    return S, n / np.where(nn > 0, nn, 1.0), nn[:, 0]
+
+
+def near_surface_queries(P: Patches3D, rng: Rng, n, t_max=1e-2, chunk=65536):
     """Points S(u,v) + t*n(u,v): patch chosen area-weighted, (u,v) uniform and
-    rejected inside the trim holes, t ~ U(-t_max, t_max)."""
+    rejected inside the circular trim holes, t ~ U(-t_max, t_max)."""
+    cps = P.cp_xyz.reshape(-1, 4, 4, 3)
+    ws = P.cp_w.reshape(-1, 4, 4)
     g = (np.arange(4) + 0.5) / 4
-    uu, vv = np.meshgrid(g, g, indexing="ij")
-    areas = np.empty(P.n)
-    for i in range(P.n):
-        _, _, jac = eval_patch(P.cp_xyz[i], P.cp_w[i], uu, vv)
-        areas[i] = jac.mean()
+    gu, gv = [a.ravel() for a in np.meshgrid(g, g, indexing="ij")]
+    areas = np.zeros(P.n)
+    for k in range(16):
+        _, _, jac = _eval_batch(cps, ws, np.full(P.n, gu[k]), np.full(P.n, gv[k]))
+        areas += jac / 16
     cdf = np.cumsum(areas)
     cdf /= cdf[-1]
-    holes = []
+    # circular holes: groups of four rational quadratic arcs (middle weight != 1)
+    hc = np.zeros((P.n, 3, 2))
+    hr = np.zeros((P.n, 3))
     for i in range(P.n):
-        hs = []
-        for uv, w in P.trims(i):
-            if uv.shape[0] == 3 and abs(w[1] - 1.0) > 1e-12:   # quadratic circle arc
-                hs.append(uv)
-        # group arcs four by four: centre = mean of arc endpoints
-        circ = []
-        for k in range(0, len(hs), 4):
-            ends = np.array([a[0] for a in hs[k:k + 4]])
+        arcs = [uv for uv, wt in P.trims(i) if uv.shape[0] == 3 and abs(wt[1] - 1.0) > 1e-12]
+        for k in range(0, min(len(arcs), 12), 4):
+            ends = np.array([a[0] for a in arcs[k:k + 4]])
             c = ends.mean(axis=0)
-            circ.append((c, np.linalg.norm(ends[0] - c)))
-        holes.append(circ)
+            hc[i, k // 4] = c
+            hr[i, k // 4] = np.linalg.norm(ends[0] - c)
     out = np.empty((n, 3))
     filled = 0
     while filled < n:
-        m = n - filled
+        m = min(n - filled, chunk)
         pid = np.minimum(np.searchsorted(cdf, rng.uniform(m)), P.n - 1)
         u = rng.uniform(m)
         v = rng.uniform(m)
         t = rng.uniform(m, -t_max, t_max)
-        keep = np.ones(m, bool)
-        for k in range(m):
-            for c, r in holes[pid[k]]:
-                if (u[k] - c[0]) ** 2 + (v[k] - c[1]) ** 2 < r * r:
-                    keep[k] = False
-                    break
-        for k in np.nonzero(keep)[0]:
-            S, nrm, _ = eval_patch(P.cp_xyz[pid[k]], P.cp_w[pid[k]], u[k], v[k])
-            out[filled] = S + t[k] * nrm
-            filled += 1
+        d2 = (u[:, None] - hc[pid, :, 0]) ** 2 + (v[:, None] - hc[pid, :, 1]) ** 2
+        keep = ~np.any(d2 < hr[pid] ** 2, axis=1)
+        pid, u, v, t = pid[keep], u[keep], v[keep], t[keep]
+        S, nrm, _ = _eval_batch(cps[pid], ws[pid], u, v)
+        q = S + t[:, None] * nrm
+        k = min(q.shape[0], n - filled)
+        out[filled:filled + k] = q[:k]
+        filled += k
     return out
 
 

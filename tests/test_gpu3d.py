@@ -1,0 +1,176 @@
+"""GPU parity of the 3D query path against the CPU oracle and closed forms.
+Every call goes through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2605_19200_amd import gwn as G
+from paper_2605_19200_amd import presets
+from paper_2605_19200_amd import workloads as W
+from tests.test_oracle3d import bilinear_patch, patches, vos
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+BAND = 1e-3
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def run(model, q):
+    out, ins = model.query(dev(q))
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ins.cpu().numpy()
+
+
+def check(w, ins, ref, tol=TOL):
+    err = np.abs(w - ref)
+    assert np.all(np.isfinite(w))
+    assert err.max() <= tol, f"max |dw| = {err.max():.3e} at {int(np.argmax(err))}"
+    sure = np.abs(ref - 0.5) > BAND
+    assert np.array_equal(ins[sure].astype(bool), (ref >= 0.5)[sure])
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    return W.Patches3D.from_list([(cp, w, []) for cp, w in W.bodies(0, [("sphere", (0, 0, 0), 1.0)], disp=0.0)])
+
+
+def sphere_points(sphere, rng, k):
+    idx = rng.integers(k, 0, sphere.n - 1)
+    uv = rng.uniform((k, 2), 0.05, 0.95)
+    S, n = [], []
+    for i, (a, b) in zip(idx, uv):
+        s, nn, _ = W.eval_patch(sphere.cp_xyz[i], sphere.cp_w[i], a, b)
+        S.append(s)
+        n.append(nn)
+    return np.array(S), np.array(n)
+
+
+def test_sphere_all_direct(sphere):
+    m = G.Model(sphere, presets.params(presets.FP64_3D, beta=1e8))
+    rng = W.Rng(41, "sph")
+    d = rng.uniform((64, 3), -1, 1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    w, _ = run(m, d * rng.uniform(64, 0.0, 0.95)[:, None])
+    assert np.abs(w - 1).max() < 1e-9
+    w, _ = run(m, d * rng.uniform(64, 1.05, 3.0)[:, None])
+    assert np.abs(w).max() < 1e-9
+    S, n = sphere_points(sphere, rng, 48)
+    for dd in [1e-2, 1e-4, 1e-6]:
+        wi, _ = run(m, S - dd * n)
+        wo, _ = run(m, S + dd * n)
+        assert np.abs(wi - 1).max() < 1e-8 and np.abs(wo).max() < 1e-8, dd
+    w, _ = run(m, S)
+    assert np.abs(w - 0.5).max() < 1e-7
+
+
+def test_sphere_fp64_form(sphere, oracle):
+    m = G.Model(sphere, presets.params(presets.FP64_3D))
+    rng = W.Rng(42, "sph")
+    S, n = sphere_points(sphere, rng, 32)
+    q = np.concatenate([S - 1e-3 * n, S + 2e-2 * n, rng.uniform((32, 3), -1.5, 1.5)])
+    w, ins = run(m, q)
+    check(w, ins, oracle.gwn3d(sphere, q))
+
+
+def test_closed_forms_triangle_and_holed_plate():
+    rng = W.Rng(43, "cf")
+    A, B, C = np.array([[0, 0, 0], [1, 0.1, 0], [0.2, 1, 0.1]])
+    m = G.Model(patches((*bilinear_patch(A, B, C, C), [])), presets.params(presets.FP64_3D, beta=1e8))
+    qs = rng.uniform((64, 3), -1, 1.5)
+    w, _ = run(m, qs)
+    ref = np.array([vos(A, B, C, q) for q in qs]) / (4 * math.pi)
+    assert np.abs(w - ref).max() < 1e-9
+    cp, wt = bilinear_patch((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0))
+    c, R = (0.5, 0.45), 0.2
+    m = G.Model(patches((cp, wt, W.square_trim() + W.circle_trim(c, R, ccw=False))),
+                presets.params(presets.FP64_3D, beta=1e8))
+    hs = np.array([0.001, 0.05, 0.3, -0.2, -1e-5])
+    q = np.stack([np.full(hs.shape, c[0]), np.full(hs.shape, c[1]), hs], 1)
+    w, _ = run(m, q)
+    for k, h in enumerate(hs):
+        sq = vos((0, 0, 0), (1, 0, 0), (1, 1, 0), q[k]) + vos((0, 0, 0), (1, 1, 0), (0, 1, 0), q[k])
+        disk = -math.copysign(1.0, h) * 2 * math.pi * (1 - abs(h) / math.hypot(h, R))
+        assert abs(w[k] - (sq - disk) / (4 * math.pi)) < 1e-9, h
+
+
+@pytest.fixture(scope="module")
+def cfg3(oracle):
+    P, q = W.config3()
+    idx = W.Rng(44, "s3").permutation(q.shape[0])[:96]
+    near = W.near_surface_queries(P, W.Rng(44, "n3"), 48)
+    qs = np.concatenate([q[idx], near])
+    return P, q, qs, oracle.gwn3d(P, qs)
+
+
+def test_config3_fp64_sampled(cfg3):
+    P, q, qs, ref = cfg3
+    m = G.Model(P, presets.params(presets.FP64_3D))
+    w, ins = run(m, qs)
+    check(w, ins, ref)
+
+
+def test_config3_full_grid_subset_consistent(cfg3):
+    """The full 128^3 launch gives the same values as the sampled call."""
+    P, q, qs, ref = cfg3
+    m = G.Model(P, presets.params(presets.FP64_3D))
+    w_full, _ = run(m, q)
+    idx = W.Rng(44, "s3").permutation(q.shape[0])[:96]
+    assert np.array_equal(w_full[idx], run(m, q[idx])[0])
+    check(w_full[idx], (w_full[idx] >= 0.5).astype(np.uint8), ref[:96])
+
+
+@pytest.fixture(scope="module")
+def cfg4(oracle):
+    P = W.cad_assembly(4, n_bodies=10)
+    lo, hi = P.bbox()
+    near = W.near_surface_queries(P, W.Rng(45, "n4"), 40)
+    uni = W.bbox_queries_uniform(W.Rng(45, "u4"), lo, hi, 40, 1.0)
+    qs = np.concatenate([near, uni])
+    return P, qs, oracle.gwn3d(P, qs)
+
+
+def test_config4_fp64_and_mixed(cfg4):
+    P, qs, ref = cfg4
+    m = G.Model(P, presets.params(presets.FP64_3D))
+    w, ins = run(m, qs)
+    check(w, ins, ref)
+    mm = G.Model(P, presets.params(presets.MIXED_3D))
+    wm, insm = run(mm, qs)
+    assert np.abs(wm - ref).max() < 5e-3
+    sure = np.abs(ref - 0.5) > BAND
+    assert np.array_equal(insm[sure].astype(bool), (ref >= 0.5)[sure])
+
+
+def test_batch_bitwise_3d(cfg4, sphere):
+    P, qs, _ = cfg4
+    m1 = G.Model(P, presets.params(presets.FP64_3D))
+    m2 = G.Model(sphere, presets.params(presets.MIXED_3D))
+    q2 = W.Rng(46, "b").uniform((100, 3), -1.2, 1.2)
+    s1, _ = run(m1, qs)
+    s2, _ = run(m2, q2)
+    parts = [(m1, qs[:30]), (m2, q2[:64]), (m1, qs[30:]), (m2, q2[64:])]
+    pts = np.concatenate([p for _, p in parts])
+    off = np.cumsum([0] + [p.shape[0] for _, p in parts])
+    out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+    G.gwn_query_batch([m.h for m, _ in parts], off, dev(pts), out, None)
+    torch.cuda.synchronize()
+    w = out.cpu().numpy()
+    assert np.array_equal(w[off[0]:off[1]], s1[:30]) and np.array_equal(w[off[2]:off[3]], s1[30:])
+    assert np.array_equal(w[off[1]:off[2]], s2[:64]) and np.array_equal(w[off[3]:off[4]], s2[64:])
+
+
+def test_empty_and_ragged_3d(sphere):
+    m = G.Model(W.Patches3D.from_list([]), presets.params(presets.FP64_3D))
+    w, _ = run(m, np.ones((5, 3)))
+    assert np.all(w == 0)
+    m = G.Model(sphere, presets.params(presets.FP64_3D))
+    q = W.Rng(47, "r").uniform((200, 3), -1.5, 1.5)
+    full, _ = run(m, q)
+    for n in [1, 63, 65, 129]:
+        assert np.array_equal(run(m, q[:n])[0], full[:n])

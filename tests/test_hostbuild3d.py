@@ -1,0 +1,100 @@
+"""Host preprocessing of 3D models (Alg. 1: subdivision, Green-scattered
+Gauss-Legendre moments, BVH, up-sweep, centering) checked on the CPU."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_19200_amd import gwn as G
+from paper_2605_19200_amd import workloads as W
+from tests.test_oracle3d import bilinear_patch, patches
+
+
+def build(P, **kw):
+    h = G.gwn_build3d(P, G.gwn_default_params(device=-1, **kw))
+    out = {k: G.gwn_inspect(h, v) for k, v in [("summary", G.GWN_I_SUMMARY), ("leaves", G.GWN_I_LEAVES),
+                                                ("nodes", G.GWN_I_NODES), ("M", G.GWN_I_MOMENTS),
+                                                ("U", G.GWN_I_UNCENTERED)]}
+    G.gwn_free(h)
+    return out
+
+
+@pytest.mark.parametrize("centre,radius", [((0, 0, 0), 1.0), ((1.0, 2.0, -0.5), 0.6)])
+def test_closed_sphere_moment_identities(centre, radius):
+    """Divergence theorem on a closed outward surface: int n = 0,
+    int x_i n_j = V delta_ij, int x_i x_j n_k = V (delta_ik c_j + delta_jk c_i)."""
+    P = W.Patches3D.from_list([(cp, w, []) for cp, w in
+                               W.bodies(0, [("sphere", centre, radius)], disp=0.0)])
+    B = build(P)
+    U = B["U"][0]
+    V = 4 / 3 * math.pi * radius ** 3
+    c = np.array(centre, float)
+    I = np.eye(3)
+    assert np.abs(U[:3]).max() < 1e-10
+    assert np.abs(U[3:12].reshape(3, 3) - V * I).max() < 1e-9 * max(1, V)
+    ref = V * (I[:, None, :] * c[None, :, None] + I[None, :, :] * c[:, None, None])
+    assert np.abs(U[12:].reshape(3, 3, 3) - ref).max() < 1e-9 * max(1, np.abs(ref).max())
+    # the centroid of a sphere's surface is its centre
+    assert np.abs(B["nodes"][0, 3:6] - c).max() < 1e-9
+
+
+def test_subdivision_of_large_patch_and_moment_sum():
+    big = bilinear_patch((0, 0, 0), (4, 0, 0.5), (4, 4, 0), (0, 4, 0.3))
+    small = bilinear_patch((1, 1, 1), (1.2, 1, 1), (1.2, 1.2, 1), (1, 1.2, 1))
+    B = build(patches((*big, []), (*small, [])))
+    leaves = B["leaves"]
+    diag = B["summary"][0][5]
+    pts = leaves[:, 1:].reshape(-1, 16, 4)
+    eu = pts[..., :3] / pts[..., 3:4]
+    d = np.linalg.norm(eu.max(1) - eu.min(1), axis=1)
+    assert np.all(d < 0.1 * diag)
+    assert np.sum(leaves[:, 0] == 0) > 4 and np.sum(leaves[:, 0] == 1) == 1
+    # moments of the subdivided big patch equal those of the unsplit patch
+    whole = build(patches((*big, [])), max_diag_frac=10.0)["U"][0]
+    split = build(patches((*big, [])))["U"][0]
+    assert np.abs(split - whole).max() < 1e-10 * np.abs(whole).max()
+
+
+def test_trimmed_patch_not_split_and_validation():
+    cp, w = bilinear_patch((0, 0, 0), (4, 0, 0), (4, 4, 0), (0, 4, 0))
+    trims = W.square_trim() + W.circle_trim((0.5, 0.5), 0.2)
+    B = build(patches((cp, w, trims), (*bilinear_patch((5, 5, 5), (5.1, 5, 5), (5.1, 5.1, 5), (5, 5.1, 5)), [])))
+    assert np.sum(B["leaves"][:, 0] == 0) == 1
+    # flat square with a hole: int n dA = (area of square - hole) * normal, exact up to quadrature
+    U = build(patches((cp, w, trims)))["U"][0]
+    assert abs(U[2] - 16 * (1 - math.pi * 0.04)) < 1e-9 and abs(U[0]) < 1e-12 and abs(U[1]) < 1e-12
+    for bad in ["open", "outside", "degree"]:
+        t = [(uv.copy(), wt.copy()) for uv, wt in trims]
+        if bad == "open":
+            t = t[:3]
+        if bad == "outside":
+            t[5] = (t[5][0] + 0.9, t[5][1])
+        if bad == "degree":
+            t[0] = (np.array([[0, 0], [0.3, 0], [0.6, 0], [1, 0.0]]), np.ones(4))
+        with pytest.raises(G.GwnError) as ei:
+            build(patches((cp, w, t)))
+        assert ei.value.status == G.GWN_EINVAL
+
+
+def test_upsweep_and_centering_3d():
+    P, _ = W.config3(grid=0)
+    P = P.subset(range(0, 4096, 37))
+    B = build(P)
+    nodes, U, M = B["nodes"], B["U"], B["M"]
+
+    def subtree(i):
+        if nodes[i, 0]:
+            return [i]
+        return subtree(int(nodes[i, 1])) + subtree(int(nodes[i, 2]))
+    for i in range(0, nodes.shape[0], 5):
+        if nodes[i, 0]:
+            continue
+        ref = sum(U[j] for j in subtree(i))
+        assert np.allclose(U[i], ref, rtol=1e-12, atol=1e-14)
+        c = nodes[i, 3:6]
+        U0, U1, U2 = U[i][:3], U[i][3:12].reshape(3, 3), U[i][12:].reshape(3, 3, 3)
+        M1 = U1 - np.outer(c, U0)
+        M2 = U2 - c[:, None, None] * U1[None, :, :] - c[None, :, None] * U1[:, None, :] \
+            + c[:, None, None] * c[None, :, None] * U0[None, None, :]
+        assert np.allclose(M[i][3:12], M1.ravel(), atol=1e-12)
+        assert np.allclose(M[i][12:], M2.ravel(), atol=1e-12)
