@@ -97,12 +97,53 @@ __global__ __launch_bounds__(kBlock) void k_keys(LaunchTable T, int dim, const d
 // ---------------------------------------------------------------------------
 // Signed angle at q (the origin of the translated frame) from a to b; 0 when
 // q lies on the segment (the direct value of a straight piece through q).
+// 1 / d for normal d > 0: hardware reciprocal refined by two Newton steps
+// (within an ulp or two; no IEEE division sequence).
+__device__ __forceinline__ double fast_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
+__device__ __forceinline__ float fast_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// atan2(y, x) for finite (x, y) != (0, 0), absolute error ~1e-15.
+// Octant reduction to t = min/max in [0, 1], then (t - 1) / (t + 1) above
+// tan(pi/8), so the polynomial runs on |r| <= tan(pi/8); one division by a
+// refined hardware reciprocal.  Coefficients: atan_coeffs.py.
+__device__ __forceinline__ double fast_atan2(double y, double x)
+{
+    constexpr double kAtanP[10] = {
+        0.99999999999999933,  -0.33333333333221649, 0.19999999978414348,  -0.1428571266185861,
+        0.11111048822077878,  -0.090895287796835464, 0.076735172520470213, -0.065058395774881372,
+        0.05024193570775376,  -0.025307491891893075};
+    const double ax = fabs(x), ay = fabs(y);
+    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
+    const bool big = mn > 0.41421356237309503 * mx;
+    double num = big ? mn - mx : mn;
+    double den = big ? mn + mx : mx;
+    if (den < 0x1p-900) { num *= 0x1p900; den *= 0x1p900; }   // keep the reciprocal normal
+    const double rd = fast_rcp(den);
+    double r = num * rd;
+    r = fma(rd, fma(-den, r, num), r);
+    const double s2 = r * r;
+    double p = kAtanP[9];
+#pragma unroll
+    for (int k = 8; k >= 1; --k) p = fma(p, s2, kAtanP[k]);
+    double a = fma(r * s2, p, r * kAtanP[0]);
+    if (big) a += 0.78539816339744831;
+    if (ay > ax) a = 1.5707963267948966 - a;
+    if (x < 0.0) a = 3.1415926535897931 - a;
+    return copysign(a, y);
+}
+
 __device__ __forceinline__ double chord_angle(double ax, double ay, double bx, double by)
 {
     double cr = ax * by - ay * bx;
     double dt = ax * bx + ay * by;
     if (cr == 0.0 && dt <= 0.0) return 0.0;
-    return atan2(cr, dt);
+    return fast_atan2(cr, dt);
 }
 
 // Sum of the chord angles seen from q (direct leaf contributions).
@@ -119,7 +160,7 @@ __device__ __forceinline__ void angle_init(AngleAcc &A) { A.sum = 0.0; A.extra =
 __device__ __forceinline__ void angle_add_chord(AngleAcc &A, double cr, double dt)
 {
     if (cr == 0.0 && dt <= 0.0) return;   // q on the chord or at an end point
-    A.sum += atan2(cr, dt);
+    A.sum += fast_atan2(cr, dt);
 }
 
 __device__ __forceinline__ double angle_total(const AngleAcc &A) { return A.sum + A.extra; }
@@ -239,7 +280,7 @@ __device__ void leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__ p
 template <typename T>
 __device__ __forceinline__ T taylor2d(T dx, T dy, T d2, const T *m, int order)
 {
-    const T inv = T(1) / d2;
+    const T inv = fast_rcp(d2);   // d2 > beta^2 r^2 > 0 for an accepted cluster
     const T ur = dx * inv, ui = -dy * inv;
     T tr = m[2 * order], ti = m[2 * order + 1];
     for (int k = order - 1; k >= 0; --k) {
@@ -314,15 +355,14 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     return (angle_total(A) + acc) * (1.0 / (2.0 * kPi));
 }
 
-// Main query kernel (2D): one wave per 64 consecutive sorted queries of one
+// Query body (2D): one wave per 64 consecutive sorted queries of one
 // segment.  Mixed-precision segments run the FP32 far-field pass and then
 // re-evaluate in FP64 the lanes with |w - 0.5| < band.
-template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double *__restrict__ pts,
-                                                    const int32_t *__restrict__ perm, double *__restrict__ out_w,
-                                                    uint8_t *__restrict__ out_in, long long *counters)
+template <bool COUNT, bool MIXED>
+__device__ __forceinline__ void query2d_body(const LaunchTable &T, const double *__restrict__ pts,
+                                             const int32_t *__restrict__ perm, double *__restrict__ out_w,
+                                             uint8_t *__restrict__ out_in, long long *counters, StackLDS &S)
 {
-    __shared__ StackLDS S;
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int wave = blockIdx.x * kWavesPerBlock + w;
@@ -348,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double 
     for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
     bool overflow = false;
     double wq;
-    const bool mixed = M.precision == GWN_MIXED;
+    const bool mixed = MIXED && M.precision == GWN_MIXED;
     if (mixed) {
         // FP32 far-field pass, then the FP64 form for the lanes of this wave
         // whose value lies within the band around 0.5 (Morton neighbours, so
@@ -374,6 +414,28 @@ __global__ __launch_bounds__(kBlock) void k_query2d(LaunchTable T, const double 
         if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
     }
     flush_counters<COUNT>(ctr, counters);
+}
+
+// Launches without mixed segments use k_query2d: without the FP32 pass the
+// kernel fits 96 VGPRs, i.e. five waves per SIMD.  k_query2d_mixed carries
+// both passes.
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_query2d(
+    LaunchTable T, const double *__restrict__ pts, const int32_t *__restrict__ perm, double *__restrict__ out_w,
+    uint8_t *__restrict__ out_in, long long *counters)
+{
+    __shared__ StackLDS S;
+    query2d_body<COUNT, false>(T, pts, perm, out_w, out_in, counters, S);
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void k_query2d_mixed(LaunchTable T, const double *__restrict__ pts,
+                                                          const int32_t *__restrict__ perm,
+                                                          double *__restrict__ out_w, uint8_t *__restrict__ out_in,
+                                                          long long *counters)
+{
+    __shared__ StackLDS S;
+    query2d_body<COUNT, true>(T, pts, perm, out_w, out_in, counters, S);
 }
 
 // 3D kernels live in query3d.hip
@@ -497,12 +559,24 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
         prof_begin(stream, ev0);
         if (dim == 2) {
             const int grid_w = (T.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
-            if (counters)
-                hipLaunchKernelGGL(k_query2d<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
-                                   (long long *)counters);
-            else
-                hipLaunchKernelGGL(k_query2d<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
-                                   nullptr);
+            bool any_mixed = false;
+            for (int j = 0; j < T.n_seg; ++j) any_mixed |= T.models[T.seg_model[j]].precision == GWN_MIXED;
+            long long *ctrs = (long long *)counters;
+            if (any_mixed) {
+                if (ctrs)
+                    hipLaunchKernelGGL(k_query2d_mixed<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out,
+                                       ow, oi, ctrs);
+                else
+                    hipLaunchKernelGGL(k_query2d_mixed<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out,
+                                       ow, oi, ctrs);
+            } else {
+                if (ctrs)
+                    hipLaunchKernelGGL(k_query2d<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
+                                       ctrs);
+                else
+                    hipLaunchKernelGGL(k_query2d<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow,
+                                       oi, ctrs);
+            }
             e = hipGetLastError();
             if (e != hipSuccess) st = hip_err(e, "query launch", err);
         } else {
