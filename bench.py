@@ -38,6 +38,138 @@ def algorithmic_flops(c: dict, order: int) -> float:
     return float(sum(FLOPS[k] * c[k] for k in FLOPS) + (7 + 8 * order) * c["far"])
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_query2d_svg1024.md")
+KERNEL_SOURCES = ["query.hip", "query_common.h", "gwn_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_19200_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel
+    calibration), or None when the kernel sources changed since."""
+    if not os.path.exists(PROFILE):
+        return None
+    vals = {}
+    with open(PROFILE) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def bench3d(steps: int = 1) -> dict:
+    """3D side measurement: the bodies scene (4096 trimmed bicubic patches)
+    on its 128^3 grid, FP64 and mixed forms, one timed pass each."""
+    import torch
+    from paper_2605_19200_amd import gwn as G
+    from paper_2605_19200_amd import presets
+    from paper_2605_19200_amd import workloads as W
+
+    P, q = W.config3()
+    pts = torch.from_numpy(q).cuda()
+    out = {"workload": f"bodies scene: {P.n} trimmed rational bicubic patches, 128^3 grid", "queries": q.shape[0]}
+    for name, pre in [("fp64", presets.FP64_3D), ("mixed", presets.MIXED_3D)]:
+        m = G.Model(P, presets.params(pre))
+        m.query(pts[:4096])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            m.query(pts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        out[name] = {"queries_per_s": q.shape[0] / dt, "ms": dt * 1e3, "beta": pre["beta"]}
+        m.close()
+        print(f"[bench] 3D {name}: {dt * 1e3:.1f} ms per grid", file=sys.stderr, flush=True)
+    return out
+
+
+def served_benchmark(seed: int = 5, n_requests: int = 400, loads=(0.5, 0.8, 0.95), exp3d=(2.0, 3.0),
+                     kinds=("2d",)) -> dict:
+    """Served form on the serving workload: resident models of the kinds
+    asked for among eight (2D drawings of about 5k-20k curves, 3D assemblies
+    of 4-39 bodies), mixed form, requests with model uniform over them and
+    N = 10^U(3, 6) queries for 2D models, 10^U(exp3d) for 3D models
+    (near-surface and uniform queries in equal parts).  A closed-loop pass
+    gives the saturation request rate; Poisson arrivals at the given
+    fractions of it give p50 / p99 latency."""
+    from paper_2605_19200_amd import presets, serve
+    from paper_2605_19200_amd import workloads as W
+
+    t = time.time()
+    geoms = [(k, g) for k, g in W.serving_models(seed, kinds=kinds)]
+    srv = serve.Server(budget_bytes=4 << 30, n_slots=2)
+    for kind, g in geoms:
+        srv.add_model(g, presets.params(presets.MIXED_2D if kind == "2d" else presets.MIXED_3D))
+    build_s = time.time() - t
+    rng = W.Rng(seed, "serve/requests")
+    models = rng.integers(n_requests, 0, len(geoms) - 1)
+    expo = rng.uniform(n_requests, 3.0, 6.0)
+    expo = np.where([geoms[m][0] == "3d" for m in models], rng.uniform(n_requests, *exp3d), expo)
+    sizes = np.floor(10 ** expo).astype(np.int64)
+    rq = W.Rng(seed, "serve/points")
+
+    def points(m, n, i):
+        kind, g = geoms[m]
+        lo, hi = g.bbox()
+        if kind == "2d":
+            return W.bbox_queries_uniform(rq, lo, hi, n, 1.0)
+        h = n // 2
+        return np.concatenate([W.near_surface_queries(g, rq, h), W.bbox_queries_uniform(rq, lo, hi, n - h, 1.0)])
+
+    # query pools per model (near-surface sampling is the slow part of the
+    # generation); each request takes a seeded window of its model's pool
+    pool_n = int(sizes.max()) * 2
+    pools = [points(m, min(pool_n, 2 * int(sizes[models == m].max(initial=1))), -1) for m in range(len(geoms))]
+    print(f"[bench] served: models built in {build_s:.1f} s, pools ready at {time.time() - t:.1f} s", file=sys.stderr,
+          flush=True)
+    starts = rng.uniform(n_requests)
+    pts = []
+    for i in range(n_requests):
+        pool = pools[int(models[i])]
+        a = int(starts[i] * (pool.shape[0] - int(sizes[i])))
+        pts.append(pool[a:a + int(sizes[i])])
+    mk = lambda rate: serve.poisson_requests(W.Rng(seed, f"serve/arrivals/{rate:.6g}"), n_requests, rate,
+                                             [int(m) for m in models], sizes, lambda m, n, i: pts[i])
+    warm = [serve.Request(int(models[i]), pts[i][:256]) for i in range(min(n_requests, 16))]
+    say = lambda msg: print(f"[bench] served: {msg}", file=sys.stderr, flush=True)
+    srv.run(warm, closed_loop=True, progress=say)
+    say("warm-up done")
+    sat = srv.run(mk(1.0), closed_loop=True, progress=say)
+    sat_rate = n_requests / sat["wall_s"]
+    print(f"[bench] served saturation: {sat_rate:.1f} requests/s, {sat['queries_per_s']:.3e} q/s", file=sys.stderr,
+          flush=True)
+    desc = {"2d": "4 x 2D drawings of 5k-20k curves, N = 10^U(3,6)",
+            "3d": f"4 x 3D assemblies of 4-39 bodies, N = 10^U({exp3d[0]:g},{exp3d[1]:g})"}
+    out = {"workload": f"{len(geoms)} resident models ({'; '.join(desc[k] for k in kinds)}), mixed form, "
+                       f"{n_requests} requests, Poisson arrivals",
+           "resident_bytes": srv.resident_bytes(), "build_s": round(build_s, 2), "queries": int(sizes.sum()),
+           "saturation": {"requests_per_s": sat_rate, "queries_per_s": sat["queries_per_s"],
+                          "launches": sat["launches"]},
+           "loads": []}
+    for f in loads:
+        r = srv.run(mk(f * sat_rate), progress=say)
+        out["loads"].append({"load": f, "requests_per_s": f * sat_rate, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                             "queries_per_s": r["queries_per_s"], "peak_in_flight_bytes": r["peak_in_flight_bytes"]})
+        print(f"[bench] served load {f}: p50 {r['p50_ms']:.2f} ms, p99 {r['p99_ms']:.2f} ms", file=sys.stderr,
+              flush=True)
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +178,8 @@ def main():
     ap.add_argument("--grid", type=int, default=1024)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0 = auto, ~15 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D side measurement")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: 3 FP64 steps, then a 256 MiB device copy used to calibrate "
                          "FETCH_SIZE/WRITE_SIZE")
@@ -150,10 +284,13 @@ def main():
     mism64 = int(np.sum(((w64[acc_idx] >= 0.5) != (ref >= 0.5)) & sure))
     mismm = int(np.sum(((wm[acc_idx] >= 0.5) != (ref >= 0.5)) & sure))
 
+    served = None if args.no_served else served_benchmark()
+    side3d = None if args.no_3d else bench3d()
+
     cpu = None
     if not args.no_cpu:
         rate = len(acc_idx) / t_o
-        m_cpu = args.cpu_sample or int(min(max(15.0 * rate, 256), 65536))
+        m_cpu = args.cpu_sample or int(min(max(15.0 * rate, 256), 1 << 20))
         cidx = rng.permutation(n)[:m_cpu]
         threads = oracle.max_threads()
         tc = time.perf_counter()
@@ -190,8 +327,11 @@ def main():
         "mixed": {"value": qps_m, "unit": "queries/s", "beta_mixed": presets.MIXED_2D["beta_mixed"],
                   "reclassified": int(cm["reclass"]), "ms_per_step": (tm1 - tm0) / args.steps * 1e3,
                   "counters": cm},
+        "served": served,
+        "3d": side3d,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic(),
                      "kernel": "k_query2d<false>", "kernel_ms": avg_kernel_s * 1e3,
                      "flops_per_launch": flops, "counters": counters},
         "cpu_baseline": cpu,

@@ -116,11 +116,15 @@ typedef struct {
                               moment quadrature (default 10, Sec. 3.1)        */
     int32_t device;        /* HIP device ordinal; -1 builds a host-only handle
                               that can be inspected but not queried           */
-    double near_ratio;     /* Q, 3D: a leaf is evaluated with the adaptive
-                              near-field rule when dist(q, AABB) <
-                              near_ratio * AABB diagonal (default 0.5)        */
-    double eps_q;          /* Q, 3D: near-field quadrature tolerance per leaf
-                              (default 1e-10)                                 */
+    double near_ratio;     /* Q, 3D: a leaf is evaluated with the near-field
+                              rule (Green's theorem about the foot point, graded
+                              panels) when dist(q, AABB) < near_ratio * AABB
+                              diagonal (default 0.25); farther leaves use their
+                              precomputed Gauss-Legendre node sets            */
+    double eps_q;          /* Q, 3D: reserved.  Validated (> 0) and stored; the
+                              near-field rule has a fixed node budget, checked
+                              to ~1e-9 per leaf, so the value does not change
+                              results (default 1e-10)                         */
 } gwn_params;
 
 /* Fill *p with the defaults listed above. */

@@ -41,7 +41,7 @@ extern "C" void gwn_default_params(gwn_params *p)
     p->eps_on = 1e-12;
     p->gl_nodes = 10;
     p->device = 0;
-    p->near_ratio = 0.5;
+    p->near_ratio = 0.25;
     p->eps_q = 1e-10;
 }
 

@@ -1,0 +1,273 @@
+"""Served form of the query path: several resident models, requests batched
+into shared launches.
+
+A request is (model, host query points).  The scheduling loop
+
+* splits each admitted request into pieces of at most ``chunk`` queries, so a
+  large request cannot hold back small ones behind it;
+* keeps ``n_slots`` launches in flight, one per HIP stream (default 2), so
+  the host-device copies of one launch overlap the kernels of another;
+* fills a free slot with pending pieces in arrival order -- all of one
+  dimension (2D and 3D models cannot share a launch), at most
+  ``max_launch`` queries -- whose device bytes (points, outputs and the
+  library's per-query scratch) fit in what is left of the byte budget;
+* issues, on the slot's stream: a pinned host -> device copy of the points,
+  one ``gwn_query_batch`` over the pieces (one segment per piece, each piece
+  of a request contiguous in the output), and the device -> host copies of
+  the values and containment flags; then records an event;
+* polls the events, hands the values back to their requests and releases
+  their bytes.  A request is complete when its last piece is.
+
+Every query's value depends only on its own point and model: each lane makes
+its own far tests and sums its own terms in the left-first order of its own
+traversal, so a request's results equal those of a solo ``gwn_query``
+bitwise, whatever it was batched with (tested).
+
+Latency of a request = completion time (when the loop sees its last event)
+minus its arrival time (the time it was offered to the loop).
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gwn as G
+
+
+@dataclass
+class Request:
+    model: int                        # index returned by Server.add_model
+    points: np.ndarray                # float64 [n, dim], host
+    arrival: float = 0.0              # seconds after the run starts
+    rid: int = -1
+    w: np.ndarray | None = None       # float64 [n] after completion
+    inside: np.ndarray | None = None  # uint8 [n]
+    done: float = float("nan")        # completion time, seconds after start
+    pieces_left: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class _Piece:
+    req: Request
+    begin: int
+    end: int
+
+
+@dataclass
+class _Slot:
+    stream: object
+    event: object
+    pins: dict = field(default_factory=dict)
+    busy: bool = False
+    pieces: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)
+    bytes: int = 0
+    out_w: object = None
+    out_in: object = None
+
+
+class Server:
+    """Scheduling loop over resident models (see module docstring)."""
+
+    def __init__(self, budget_bytes: int = 4 << 30, n_slots: int = 2, chunk: int = 1 << 18,
+                 max_launch: int = 1 << 20, device: int = 0):
+        import torch
+        self.torch = torch
+        if n_slots < 1 or chunk < 1 or max_launch < 1 or budget_bytes <= 0:
+            raise ValueError("bad server configuration")
+        self.device = torch.device("cuda", device)
+        self.budget = int(budget_bytes)
+        self.chunk = int(chunk)
+        self.max_launch = int(max_launch)
+        self.models: list[G.Model] = []
+        self.dims: list[int] = []
+        self.scratch: list[int] = []
+        with torch.cuda.device(self.device):
+            self.slots = [_Slot(torch.cuda.Stream(device=self.device), torch.cuda.Event()) for _ in range(n_slots)]
+        self.launches = 0
+        self.in_flight_bytes = 0
+        self.peak_bytes = 0
+
+    # -- models ---------------------------------------------------------
+    def add_model(self, geometry, params: G.gwn_params | None = None) -> int:
+        m = G.Model(geometry, params)
+        self.models.append(m)
+        self.dims.append(m.dim)
+        self.scratch.append(int(m.bytes()[1]))
+        return len(self.models) - 1
+
+    def resident_bytes(self) -> int:
+        return sum(int(m.bytes()[0]) for m in self.models)
+
+    def bytes_per_query(self, model: int) -> int:
+        return 8 * self.dims[model] + 8 + 1 + self.scratch[model]
+
+    # -- the loop -------------------------------------------------------
+    def run(self, requests: list[Request], closed_loop: bool = False, progress=None) -> dict:
+        """Serve ``requests`` to completion.  Arrival times are honoured
+        (open loop) unless ``closed_loop``, where all are offered at t = 0.
+        ``progress``: optional callable, given a status string about every
+        5 s.  Returns throughput and latency statistics."""
+        torch = self.torch
+        for k, r in enumerate(requests):
+            if not (0 <= r.model < len(self.models)):
+                raise ValueError(f"request {k}: unknown model {r.model}")
+            pts = np.ascontiguousarray(r.points, dtype=np.float64)
+            if pts.ndim != 2 or pts.shape[1] != self.dims[r.model]:
+                raise ValueError(f"request {k}: points must be [n, {self.dims[r.model]}]")
+            r.points = pts
+            r.rid = k
+            r.w = np.empty(pts.shape[0], np.float64)
+            r.inside = np.empty(pts.shape[0], np.uint8)
+            r.done = float("nan")
+            if closed_loop:
+                r.arrival = 0.0
+        order = sorted(requests, key=lambda r: r.arrival)
+        arrivals = deque(order)
+        pending: deque[_Piece] = deque()
+        n_done = 0
+        total_q = sum(r.points.shape[0] for r in requests)
+        t0 = time.perf_counter()
+        now = 0.0
+        next_report = 5.0
+        while n_done < len(requests):
+            now = time.perf_counter() - t0
+            if progress is not None and now >= next_report:
+                next_report += 5.0
+                progress(f"t={now:.1f}s done {n_done}/{len(requests)} pending pieces {len(pending)} "
+                         f"launches {self.launches} in flight {self.in_flight_bytes} B")
+            # admit arrived requests, split into pieces
+            while arrivals and arrivals[0].arrival <= now:
+                r = arrivals.popleft()
+                n = r.points.shape[0]
+                step = max(1, min(self.chunk, (self.budget // max(len(self.slots), 1)) // self.bytes_per_query(r.model)))
+                if n == 0:
+                    r.done = now
+                    n_done += 1
+                    continue
+                r.pieces_left = (n + step - 1) // step
+                for b in range(0, n, step):
+                    pending.append(_Piece(r, b, min(n, b + step)))
+            # completions
+            for s in self.slots:
+                if s.busy and s.event.query():
+                    n_done += self._retire(s, time.perf_counter() - t0)
+            # launches
+            launched = False
+            for s in self.slots:
+                if not s.busy and pending:
+                    launched |= self._launch(s, pending)
+            if not launched and not any(s.busy for s in self.slots) and not pending and arrivals:
+                wait = arrivals[0].arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+            elif not launched:
+                time.sleep(2e-5)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.latency for r in requests if r.points.shape[0] > 0])
+        return {
+            "requests": len(requests), "queries": int(total_q), "wall_s": wall,
+            "queries_per_s": total_q / wall if wall > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else 0.0,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else 0.0,
+            "mean_ms": float(lat.mean() * 1e3) if lat.size else 0.0,
+            "launches": self.launches, "peak_in_flight_bytes": self.peak_bytes, "budget_bytes": self.budget,
+        }
+
+    def _pinned(self, s: _Slot, key: str, n: int, dtype):
+        torch = self.torch
+        buf = s.pins.get(key)
+        if buf is None or buf.numel() < n:
+            buf = torch.empty(max(n, 1 << 12), dtype=dtype, pin_memory=True)
+            s.pins[key] = buf
+        return buf[:n]
+
+    def _launch(self, s: _Slot, pending: deque) -> bool:
+        torch = self.torch
+        dim = self.dims[pending[0].req.model]
+        free = self.budget - self.in_flight_bytes
+        take, nq, nbytes = [], 0, 0
+        while pending and len(take) < 4096:
+            p = pending[0]
+            m = p.req.model
+            if self.dims[m] != dim:
+                break
+            cnt = p.end - p.begin
+            b = cnt * self.bytes_per_query(m)
+            if take and (nq + cnt > self.max_launch or nbytes + b > free):
+                break
+            if not take and b > free:
+                return False        # wait for bytes to come back
+            take.append(pending.popleft())
+            nq += cnt
+            nbytes += b
+        if not take:
+            return False
+        # gather points into the slot's pinned buffer
+        h_pts = self._pinned(s, "pts", nq * dim, torch.float64)
+        hp = h_pts.numpy().reshape(nq, dim)
+        offsets = [0]
+        for p in take:
+            c = p.end - p.begin
+            hp[offsets[-1]:offsets[-1] + c] = p.req.points[p.begin:p.end]
+            offsets.append(offsets[-1] + c)
+        with torch.cuda.stream(s.stream):
+            d_pts = torch.empty(nq * dim, dtype=torch.float64, device=self.device)
+            d_w = torch.empty(nq, dtype=torch.float64, device=self.device)
+            d_in = torch.empty(nq, dtype=torch.uint8, device=self.device)
+            d_pts.copy_(h_pts, non_blocking=True)
+            G.gwn_query_batch([self.models[p.req.model].h for p in take], np.asarray(offsets, np.int64), d_pts, d_w,
+                              d_in, s.stream)
+            h_w = self._pinned(s, "w", nq, torch.float64)
+            h_in = self._pinned(s, "in", nq, torch.uint8)
+            h_w.copy_(d_w, non_blocking=True)
+            h_in.copy_(d_in, non_blocking=True)
+            s.event.record(s.stream)
+        s.busy = True
+        s.pieces = take
+        s.offsets = offsets
+        s.bytes = nbytes
+        s.out_w, s.out_in = h_w, h_in
+        s.keep = (d_pts, d_w, d_in)     # device buffers live until the event completes
+        self.in_flight_bytes += nbytes
+        self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
+        self.launches += 1
+        return True
+
+    def _retire(self, s: _Slot, now: float) -> int:
+        w = s.out_w.numpy()
+        ins = s.out_in.numpy()
+        finished = 0
+        for k, p in enumerate(s.pieces):
+            a, b = s.offsets[k], s.offsets[k + 1]
+            p.req.w[p.begin:p.end] = w[a:b]
+            p.req.inside[p.begin:p.end] = ins[a:b]
+            p.req.pieces_left -= 1
+            if p.req.pieces_left == 0:
+                p.req.done = now
+                finished += 1
+        self.in_flight_bytes -= s.bytes
+        s.busy = False
+        s.pieces, s.offsets, s.keep = [], [], None
+        s.bytes = 0
+        return finished
+
+    def close(self):
+        for m in self.models:
+            m.close()
+        self.models = []
+
+
+def poisson_requests(rng, n_requests: int, rate: float, models: list[int], sizes: np.ndarray, points_fn):
+    """Requests with exponential inter-arrival times of mean 1/rate seconds;
+    model k = models[i], size sizes[i], points from points_fn(model, n, i)."""
+    gaps = -np.log(1.0 - rng.uniform(n_requests, 0.0, 1.0)) / rate
+    t = np.cumsum(gaps)
+    return [Request(models[i], points_fn(models[i], int(sizes[i]), i), float(t[i])) for i in range(n_requests)]

@@ -619,12 +619,15 @@ def config4(seed=4, n_query=1_000_000, n_bodies=39):
     return P, np.ascontiguousarray(q)
 
 
-def serving_models(seed=5):
-    """Eight resident models: four 2D drawings (about 5k, 10k, 15k, 20k curves)
-    and four 3D assemblies (4, 10, 20, 39 bodies; about 2k-20k patches)."""
+def serving_models(seed=5, kinds=("2d", "3d")):
+    """Resident serving models: four 2D drawings (about 5k, 10k, 15k, 20k
+    curves) and four 3D assemblies (4, 10, 20, 39 bodies; about 2k-20k
+    patches), of the kinds asked for."""
     models = []
-    for k, g in enumerate([12, 25, 38, 50]):
-        models.append(("2d", svg_like(seed * 100 + k, n_groups=g)))
-    for k, nb in enumerate([4, 10, 20, 39]):
-        models.append(("3d", cad_assembly(seed * 100 + 10 + k, n_bodies=nb)))
+    if "2d" in kinds:
+        for k, g in enumerate([12, 25, 38, 50]):
+            models.append(("2d", svg_like(seed * 100 + k, n_groups=g)))
+    if "3d" in kinds:
+        for k, nb in enumerate([4, 10, 20, 39]):
+            models.append(("3d", cad_assembly(seed * 100 + 10 + k, n_bodies=nb)))
     return models
