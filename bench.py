@@ -43,11 +43,15 @@ KERNEL_SOURCES = ["query.hip", "query_common.h", "gwn_internal.h"]
 
 
 def kernel_source_hash() -> str:
+    """Hash of the 2D kernel's sources with comments and blank space removed
+    (a comment edit does not invalidate the recorded counters)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2605_19200_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2605_19200_amd", "csrc", f)) as fh:
+            text = re.sub(r"//[^\n]*", "", fh.read())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

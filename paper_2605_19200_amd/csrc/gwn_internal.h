@@ -46,7 +46,7 @@ struct Prim2 {
     double h[12];
 };
 
-// 3D node, 256 bytes.  Internal: centroid, squared AABB half diagonal and the
+// 3D node, three 128-byte lines.  Internal: centroid, squared AABB half diagonal and the
 // contracted centred moments used by the order-2 expansion:
 //   t[0..2]   M0_k
 //   t[3..8]   symmetric part of M1: M1_00, M1_11, M1_22, M1_01+M1_10,
@@ -91,7 +91,9 @@ struct Trim3 {
 
 // Gauss-Legendre orders of a 3D leaf's direct rules for well-separated
 // queries, finest first, with the distance/half-diagonal ratios from which
-// each is used (error ~ rho^-2n, rho = r + sqrt(r^2 + 1), <= ~3e-9).
+// each is used (checked against the oracle: the 8- and 6-point rules hold the
+// bound at these ratios on rational trimmed patches, where the weights limit
+// the convergence of lower orders).
 constexpr int kLeafRules[3] = {12, 8, 6};
 constexpr double kLeafRuleRatio[3] = {0.0, 2.5, 6.0};
 

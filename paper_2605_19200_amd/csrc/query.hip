@@ -95,8 +95,6 @@ __global__ __launch_bounds__(kBlock) void k_keys(LaunchTable T, int dim, const d
 // ---------------------------------------------------------------------------
 // 2D leaf: direct evaluation (Sec. 3.3)
 // ---------------------------------------------------------------------------
-// Signed angle at q (the origin of the translated frame) from a to b; 0 when
-// q lies on the segment (the direct value of a straight piece through q).
 // 1 / d for normal d > 0: hardware reciprocal refined by two Newton steps
 // (within an ulp or two; no IEEE division sequence).
 __device__ __forceinline__ double fast_rcp(double d)
@@ -138,6 +136,8 @@ __device__ __forceinline__ double fast_atan2(double y, double x)
     return copysign(a, y);
 }
 
+// Signed angle at q (the origin of the translated frame) from a to b; 0 when
+// q lies on the segment (the direct value of a straight piece through q).
 __device__ __forceinline__ double chord_angle(double ax, double ay, double bx, double by)
 {
     double cr = ax * by - ay * bx;
