@@ -101,9 +101,10 @@ typedef struct {
     double beta_mixed;     /* Q: far-field factor of the FP32 pass of the mixed
                               form (default 4)                               */
     int32_t taylor_order;  /* Q: expansion order of Eq. taylor; default 2
-                              (Sec. 4.2).  3D: 0..2.  2D: 0..8 -- orders above
-                              2 carry the same expansion further (exact chord
-                              moments, complex form)                          */
+                              (Sec. 4.2).  2D: 0..8, 3D: 0..6 -- orders above
+                              2 carry the same expansion further (2D: exact
+                              chord moments in complex form; 3D: solid
+                              harmonics, see GWN_I_MULTIPOLE)                */
     int32_t precision;     /* Q: GWN_FP64 or GWN_MIXED                         */
     double reclass_band;   /* Q: mixed form: queries with |w - 0.5| < band are
                               re-evaluated in FP64 (default 1e-2)            */
@@ -212,9 +213,19 @@ gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_s
  *   GWN_I_COMPLEX   2D only, per node: the centred complex moments
  *                   m_k = integral over the cluster's chords of (z - c)^k dz,
  *                   k = 0..8, as (re, im) pairs -- 18 doubles (zero for leaves)
+ *   GWN_I_MULTIPOLE 3D only, per node: 1/r (r = AABB half diagonal), 0, then
+ *                   for l = 1..7, m = 0..l the moments
+ *                   N_l^m = -integral n . conj(grad R_l^m(x - c)) dA scaled
+ *                   by r^-(l+1), as (re, im) pairs -- 72 doubles.  R_l^m are
+ *                   the regular solid harmonics r^l P_l^m(cos t) e^{i m p} /
+ *                   (l + m)! (no Condon-Shortley phase); the solid angle of
+ *                   the cluster at q is sum_l [I_l^0 N_l^0 + 2 sum_m>0
+ *                   Re(I_l^m N_l^m)] with I_l^m(q - c) = (l - m)!
+ *                   P_l^m(cos t) e^{i m p} / |q - c|^(l+1).  The order-p far
+ *                   field (Eq. taylor) is the truncation l <= p + 1.
  */
 enum { GWN_I_SUMMARY = 0, GWN_I_LEAVES = 1, GWN_I_NODES = 2, GWN_I_MOMENTS = 3, GWN_I_UNCENTERED = 4,
-       GWN_I_COMPLEX = 5 };
+       GWN_I_COMPLEX = 5, GWN_I_MULTIPOLE = 6 };
 gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64_t capacity, int64_t *count);
 
 /* Kernel timing.  gwn_profile(1, NULL, NULL) starts recording a pair of HIP

@@ -23,6 +23,7 @@
 #include <thread>
 
 #include "gwn_internal.h"
+#include "multipole3d.h"
 
 namespace gwn {
 
@@ -314,6 +315,10 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         WC(3 * (size_t)nl, 0.0);
     std::vector<std::vector<QNode3>> qn(nl);
     std::vector<std::array<int, 3>> qcount(nl);
+    // multipole moments of each leaf about its own centroid (far field at
+    // orders above 2; see multipole3d.h)
+    std::vector<cplx> LN((size_t)nl * kMpoleTerms, cplx(0, 0));
+    std::vector<double> LC(3 * (size_t)nl, 0.0);
     // leaves are independent: split them over host threads
     auto leaf_work = [&](int li) {
         const Patch &pt = leaves[li];
@@ -372,6 +377,12 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
                     Wt[li] += area;
                     for (int a = 0; a < 3; ++a) WC[3 * li + a] += area * S[a];
                 });
+        double *cl = &LC[3 * li];
+        for (int a = 0; a < 3; ++a)
+            cl[a] = Wt[li] > 0.0 ? WC[3 * li + a] / Wt[li] : 0.5 * (LO[3 * li + a] + HI[3 * li + a]);
+        cplx *nl_out = &LN[(size_t)li * kMpoleTerms];
+        scatter(gx.data(), gw.data(), g, gx.data(), gw.data(), g,
+                [&](const QNode3 &node, double) { mpole_add_node(node.x, node.n, cl, kMaxL3, nl_out); });
     };
     {
         const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
@@ -388,6 +399,40 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     if (m.tree.depth > kStackDepth) {
         err = "BVH depth " + std::to_string(m.tree.depth) + " exceeds the traversal stack";
         return GWN_EOVERFLOW;
+    }
+    // multipole up-sweep: children follow their parent in DFS order, so a
+    // reverse sweep sees both children first; each is translated to the
+    // parent's centroid.  Stored scaled by 1/r^(l+1) (r = AABB half
+    // diagonal), which keeps the FP32 mirror in range.
+    {
+        const size_t nn = m.tree.nodes.size();
+        std::vector<cplx> NN(nn * kMpoleTerms, cplx(0, 0));
+        for (size_t ii = nn; ii-- > 0;) {
+            const HostNode &h = m.tree.nodes[ii];
+            cplx *dst = &NN[ii * kMpoleTerms];
+            if (h.is_leaf) {
+                mpole_translate(&LN[(size_t)h.leaf * kMpoleTerms], &LC[3 * (size_t)h.leaf], h.c, kMaxL3, dst);
+            } else {
+                const HostNode &a = m.tree.nodes[ii + 1], &b = m.tree.nodes[h.right];
+                mpole_translate(&NN[(ii + 1) * kMpoleTerms], a.c, h.c, kMaxL3, dst);
+                mpole_translate(&NN[(size_t)h.right * kMpoleTerms], b.c, h.c, kMaxL3, dst);
+            }
+        }
+        m.mpole.assign(nn * kMpoleStride, 0.0);
+        for (size_t ii = 0; ii < nn; ++ii) {
+            const double r = m.tree.nodes[ii].r;
+            const double ir = r > 0.0 ? 1.0 / r : 1.0;
+            double *o = &m.mpole[ii * kMpoleStride];
+            o[0] = ir;
+            for (int l = 1; l <= kMaxL3; ++l) {
+                const double sc = std::pow(ir, l + 1);
+                for (int mm = 0; mm <= l; ++mm) {
+                    const cplx v = NN[ii * kMpoleTerms + mp_index(l, mm)] * sc;
+                    o[2 + 2 * mp_index(l, mm)] = v.real();
+                    o[3 + 2 * mp_index(l, mm)] = v.imag();
+                }
+            }
+        }
     }
     // leaves in BVH leaf order
     m.leaf_src.clear();

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "gwn_internal.h"
+#include "multipole3d.h"
 
 using namespace gwn;
 
@@ -52,8 +53,8 @@ static gwn_status check_query_params(int dim, const gwn_params *p)
         return fail(GWN_EINVAL, "beta_mixed must be finite and > 0");
     if (dim == 2 && (p->beta < 2.0 || p->beta_mixed < 2.0))
         return fail(GWN_EINVAL, "2D requires beta >= 2 (chord substitution needs q outside every accepted AABB)");
-    if (p->taylor_order < 0 || p->taylor_order > (dim == 2 ? kMaxOrder2D : 2))
-        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..8 in 2D" : "taylor_order must be 0, 1 or 2 in 3D");
+    if (p->taylor_order < 0 || p->taylor_order > (dim == 2 ? kMaxOrder2D : kMaxOrder3D))
+        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..8 in 2D" : "taylor_order must be 0..6 in 3D");
     if (p->precision != GWN_FP64 && p->precision != GWN_MIXED) return fail(GWN_EINVAL, "bad precision");
     if (!(p->reclass_band >= 0) || !std::isfinite(p->reclass_band)) return fail(GWN_EINVAL, "bad reclass_band");
     if (!(p->near_ratio >= 0) || !std::isfinite(p->near_ratio)) return fail(GWN_EINVAL, "bad near_ratio");
@@ -132,11 +133,13 @@ gwn_status upload_model(Model &m, std::string &err)
 {
     hipError_t e = hipSetDevice(m.device);
     if (e != hipSuccess) { err = std::string("hipSetDevice: ") + hipGetErrorString(e); return GWN_EHIP; }
-    // Arena: nodes | prims | trims | qnodes, each 256-byte aligned.
+    // Arena: nodes | prims | trims | qnodes | mpole | fmpole, each 256-byte
+    // aligned (the last four are 3D only).
     std::vector<Node2> n2; std::vector<Prim2> p2;
     std::vector<Node3> n3; std::vector<Prim3> p3;
-    const void *src[4] = {nullptr, nullptr, nullptr, nullptr};
-    size_t bytes[4] = {0, 0, 0, 0};
+    std::vector<float> fmp;
+    const void *src[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t bytes[6] = {0, 0, 0, 0, 0, 0};
     if (m.dim == 2) {
         pack2d(m, n2, p2);
         src[0] = n2.data(); bytes[0] = n2.size() * sizeof(Node2);
@@ -147,15 +150,18 @@ gwn_status upload_model(Model &m, std::string &err)
         src[1] = p3.data(); bytes[1] = p3.size() * sizeof(Prim3);
         src[2] = m.trims.data(); bytes[2] = m.trims.size() * sizeof(Trim3);
         src[3] = m.qnodes.data(); bytes[3] = m.qnodes.size() * sizeof(QNode3);
+        fmp.assign(m.mpole.begin(), m.mpole.end());
+        src[4] = m.mpole.data(); bytes[4] = m.mpole.size() * sizeof(double);
+        src[5] = fmp.data(); bytes[5] = fmp.size() * sizeof(float);
     }
-    size_t off[5];
+    size_t off[7];
     off[0] = 0;
-    for (int k = 0; k < 4; ++k) off[k + 1] = align_up(off[k] + bytes[k], 256);
-    size_t total = std::max<size_t>(off[4], 256);
+    for (int k = 0; k < 6; ++k) off[k + 1] = align_up(off[k] + bytes[k], 256);
+    size_t total = std::max<size_t>(off[6], 256);
     void *arena = nullptr;
     e = hipMalloc(&arena, total);
     if (e != hipSuccess) { err = std::string("hipMalloc arena: ") + hipGetErrorString(e); return GWN_ENOMEM; }
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 6; ++k)
         if (bytes[k]) {
             e = hipMemcpy((char *)arena + off[k], src[k], bytes[k], hipMemcpyHostToDevice);
             if (e != hipSuccess) {
@@ -188,6 +194,8 @@ gwn_status upload_model(Model &m, std::string &err)
     m.dev.prims = (char *)arena + off[1];
     m.dev.trims = (char *)arena + off[2];
     m.dev.qnodes = (char *)arena + off[3];
+    m.dev.mpole = (char *)arena + off[4];
+    m.dev.fmpole = (char *)arena + off[5];
     m.dev.flag = flag;
     m.dev.n_nodes = (int32_t)m.tree.nodes.size();
     refresh_dev_params(m);
@@ -452,6 +460,13 @@ extern "C" gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64
         width = 2 * (kMaxOrder2D + 1);
         items = (int64_t)m.tree.nodes.size();
         buf.assign(m.cmom2.begin(), m.cmom2.end());
+        break;
+    }
+    case GWN_I_MULTIPOLE: {
+        if (d != 3) return fail(GWN_EINVAL, "multipole moments exist for 3D models only");
+        width = kMpoleStride;
+        items = (int64_t)m.tree.nodes.size();
+        buf.assign(m.mpole.begin(), m.mpole.end());
         break;
     }
     case GWN_I_MOMENTS:

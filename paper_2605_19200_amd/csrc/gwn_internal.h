@@ -28,6 +28,10 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // Leaf: m[0..3] holds the leaf's control-point AABB (lo.x, lo.y, hi.x,
 // hi.y).  The float fields mirror c, r2 and m_0..m_7 for the FP32 pass.
 constexpr int kMaxOrder2D = 8;
+constexpr int kMaxOrder3D = 6;   // harmonic degree <= 7, see multipole3d.h
+constexpr int kMaxL3 = kMaxOrder3D + 1;   // highest solid-harmonic degree
+constexpr int kMpoleTerms = 35;           // (l, m) with 1 <= l <= 7, 0 <= m <= l
+constexpr int kMpoleStride = 72;          // per node: 1/r, 0, then 35 (re, im) pairs
 struct alignas(128) Node2 {
     double c[2];
     double r2;
@@ -112,6 +116,8 @@ struct DevModel {
     const void *prims;      // Prim2* or Prim3*
     const void *trims;      // Trim3* (3D)
     const void *qnodes;     // QNode3* (3D)
+    const void *mpole;      // 3D: per node 72 doubles, 1/r then scaled multipole moments
+    const void *fmpole;     // 3D: FP32 mirror of mpole
     int32_t *flag;          // overflow flag (device)
     int32_t dim;
     int32_t n_nodes;
@@ -183,6 +189,7 @@ struct Model {
     std::vector<QNode3> qnodes;
     std::vector<int64_t> leaf_q_begin, leaf_q_count;
     std::vector<std::array<int, 3>> leaf_q_rules;
+    std::vector<double> mpole;        // 3D: per node kMpoleStride doubles (multipole3d.h)
     // device
     int device = -1;
     void *d_arena = nullptr;

@@ -78,28 +78,51 @@ __device__ double leaf3d(const DevModel &M, const Node3 *__restrict__ nd, double
     return om;
 }
 
+// Far field of an accepted cluster (Eq. taylor to order p = L - 1), as a
+// solid angle: sum over 1 <= l <= L of I_l^0 N_l^0 + 2 sum_{m>0} Re(I_l^m
+// N_l^m), with the irregular solid harmonics I_l^m(q - c) generated per m by
+//   I_m^m = I_{m-1}^{m-1} (2m - 1)(x + i y) / rho^2,  I_0^0 = 1 / rho,
+//   I_l^m = ((2l - 1) z I_{l-1}^m - (l + m - 1)(l - m - 1) I_{l-2}^m) / rho^2
+// and contracted on the fly (a handful of registers at any order).  The
+// moments are stored scaled by r^-(l+1), so the harmonics are taken at
+// (q - c) / r.  mp[0] = 1 / r, mp[2 + 2k], mp[3 + 2k] = (re, im) of moment
+// k = l (l + 1) / 2 - 1 + m.
 template <typename T>
-__device__ __forceinline__ T taylor3d(T sx, T sy, T sz, T r2, const T *t, int order)
+__device__ __forceinline__ T multipole3d(T sx, T sy, T sz, const T *__restrict__ mp, int L)
 {
-    const T inv2 = T(1) / r2;
-    const T inv1 = sqrt(inv2);
-    const T inv3 = inv1 * inv2;
-    T w = (sx * t[0] + sy * t[1] + sz * t[2]) * inv3;
-    if (order >= 1) {
-        const T tr = t[3] + t[4] + t[5];
-        const T sms = t[3] * sx * sx + t[4] * sy * sy + t[5] * sz * sz + t[6] * sx * sy + t[7] * sx * sz +
-                      t[8] * sy * sz;
-        w += tr * inv3 - T(3) * sms * inv3 * inv2;
+    const T ir = mp[0];
+    const T x = sx * ir, y = sy * ir, z = sz * ir;
+    const T inv2 = T(1) / (x * x + y * y + z * z);
+    T mmr = sqrt(inv2), mmi = T(0);
+    T omega = T(0);
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) {
+            const T f = T(2 * m - 1) * inv2;
+            const T nr = (mmr * x - mmi * y) * f;
+            const T ni = (mmr * y + mmi * x) * f;
+            mmr = nr;
+            mmi = ni;
+        }
+        const T wgt = m == 0 ? T(1) : T(2);
+        T pr = T(0), pi = T(0), cr = mmr, ci = mmi;
+        for (int l = m; l <= L; ++l) {
+            if (l > m) {
+                const T a = T(2 * l - 1) * z * inv2;
+                const T b = T((l + m - 1) * (l - m - 1)) * inv2;
+                const T nr = a * cr - b * pr;
+                const T ni = a * ci - b * pi;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+            if (l >= 1) {
+                const int k = l * (l + 1) / 2 - 1 + m;
+                omega += wgt * (cr * mp[2 + 2 * k] - ci * mp[3 + 2 * k]);
+            }
+        }
     }
-    if (order >= 2) {
-        const T es = t[9] * sx + t[10] * sy + t[11] * sz;
-        const T cub = t[12] * sx * sx * sx + t[13] * sy * sy * sy + t[14] * sz * sz * sz + t[15] * sx * sx * sy +
-                      t[16] * sx * sx * sz + t[17] * sy * sy * sx + t[18] * sy * sy * sz + t[19] * sz * sz * sx +
-                      t[20] * sz * sz * sy + t[21] * sx * sy * sz;
-        const T inv5 = inv3 * inv2;
-        w += T(0.5) * (T(-3) * es * inv5 + T(15) * cub * inv5 * inv2);
-    }
-    return w;   // solid angle (times 4 pi of w)
+    return omega;
 }
 
 template <bool F32, bool COUNT>
@@ -130,12 +153,18 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
                     const float sx = nd->fc[0] - qxf, sy = nd->fc[1] - qyf, sz = nd->fc[2] - qzf;
                     const float r2 = sx * sx + sy * sy + sz * sz;
                     far = r2 > beta2f * nd->fr2;
-                    if (far) acc_far += (double)taylor3d<float>(sx, sy, sz, r2, nd->ft, M.order);
+                    if (far)
+                        acc_far += (double)multipole3d<float>(-sx, -sy, -sz,
+                                                              (const float *)M.fmpole + (size_t)cur * kMpoleStride,
+                                                              M.order + 1);
                 } else {
                     const double sx = nd->c[0] - qx, sy = nd->c[1] - qy, sz = nd->c[2] - qz;
                     const double r2 = sx * sx + sy * sy + sz * sz;
                     far = r2 > beta2 * nd->r2;
-                    if (far) acc_far += taylor3d<double>(sx, sy, sz, r2, nd->t, M.order);
+                    if (far)
+                        acc_far += multipole3d<double>(-sx, -sy, -sz,
+                                                       (const double *)M.mpole + (size_t)cur * kMpoleStride,
+                                                       M.order + 1);
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }

@@ -20,7 +20,7 @@ GWN_OK, GWN_EINVAL, GWN_ENOMEM, GWN_EHIP, GWN_EUNSUPPORTED, GWN_EOVERFLOW = rang
 GWN_FP64, GWN_MIXED = 0, 1
 COUNTER_NAMES = ["nodes", "far", "leaves", "leaf_fast", "pieces", "angles", "reclass", "overflow"]
 GWN_NCOUNTERS = len(COUNTER_NAMES)
-GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX = range(6)
+GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX, GWN_I_MULTIPOLE = range(7)
 
 EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_set_params", "gwn_get_params", "gwn_query",
             "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
@@ -180,7 +180,7 @@ def gwn_model_bytes(h):
 
 _WIDTH = {GWN_I_SUMMARY: lambda d: 8, GWN_I_LEAVES: lambda d: 13 if d == 2 else 65, GWN_I_NODES: lambda d: 13,
           GWN_I_MOMENTS: lambda d: d + d * d + d ** 3, GWN_I_UNCENTERED: lambda d: d + d * d + d ** 3,
-          GWN_I_COMPLEX: lambda d: 18}
+          GWN_I_COMPLEX: lambda d: 18, GWN_I_MULTIPOLE: lambda d: 72}
 
 
 def gwn_inspect(h, what: int) -> np.ndarray:

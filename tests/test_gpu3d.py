@@ -174,3 +174,25 @@ def test_empty_and_ragged_3d(sphere):
     full, _ = run(m, q)
     for n in [1, 63, 65, 129]:
         assert np.array_equal(run(m, q[:n])[0], full[:n])
+
+
+def test_error_decreases_with_order_3d(cfg3):
+    """Far-field error of the bodies scene at beta = 3 falls with the
+    expansion order (orders above the paper's 2 through solid harmonics)."""
+    P, q, qs, ref = cfg3
+    errs = []
+    for order in (0, 2, 4, 6):
+        m = G.Model(P, presets.params(presets.FP64_3D, beta=3.0, taylor_order=order))
+        w, _ = run(m, qs)
+        errs.append(np.abs(w - ref).max())
+        m.close()
+    assert errs[1] < errs[0] and errs[2] < errs[1] and errs[3] < errs[2], errs
+    assert errs[3] < 1e-5
+
+
+def test_paper_order_3d(cfg3):
+    """The paper's order 2 at the beta that meets the bound."""
+    P, q, qs, ref = cfg3
+    m = G.Model(P, presets.params(presets.PAPER_ORDER_3D))
+    w, ins = run(m, qs)
+    check(w, ins, ref)

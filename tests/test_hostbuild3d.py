@@ -98,3 +98,80 @@ def test_upsweep_and_centering_3d():
             + c[:, None, None] * c[None, :, None] * U0[None, None, :]
         assert np.allclose(M[i][3:12], M1.ravel(), atol=1e-12)
         assert np.allclose(M[i][12:], M2.ravel(), atol=1e-12)
+
+
+def multipole_omega(mp, s, order):
+    """Solid angle from the GWN_I_MULTIPOLE record (1/r, 0, scaled N_l^m)
+    at s = q - c, truncated at degree order + 1."""
+    L = order + 1
+    x, y, z = np.asarray(s) * mp[0]
+    inv2 = 1.0 / (x * x + y * y + z * z)
+    xi = complex(x, y)
+    I = {}
+    for m in range(L + 1):
+        I[m, m] = np.sqrt(inv2) if m == 0 else I[m - 1, m - 1] * (2 * m - 1) * xi * inv2
+        for l in range(m + 1, L + 1):
+            prev2 = I.get((l - 2, m), 0.0)
+            I[l, m] = ((2 * l - 1) * z * I[l - 1, m] - (l + m - 1) * (l - m - 1) * prev2) * inv2
+    om = 0.0
+    for l in range(1, L + 1):
+        for m in range(l + 1):
+            k = l * (l + 1) // 2 - 1 + m
+            N = complex(mp[2 + 2 * k], mp[3 + 2 * k])
+            om += (1 if m == 0 else 2) * (I[l, m] * N).real
+    return om
+
+
+def cartesian_omega(M, s, order):
+    """Order 0..2 Taylor term of the solid angle (Eq. taylor) with the centred
+    Cartesian moments M0[3], M1[3x3], M2[3x3x3] at s = c - q."""
+    s = np.asarray(s)
+    r = np.linalg.norm(s)
+    I = np.eye(3)
+    g = s / r ** 3
+    dg = I / r ** 3 - 3 * np.outer(s, s) / r ** 5
+    ddg = -3 * (I[None, :, :] * s[:, None, None] + I[:, None, :] * s[None, :, None] + I[:, :, None] * s[None, None, :]) \
+        / r ** 5 + 15 * np.einsum("i,j,k->ijk", s, s, s) / r ** 7
+    om = g @ M[:3]
+    if order >= 1:
+        om += np.einsum("jk,jk->", dg, M[3:12].reshape(3, 3))
+    if order >= 2:
+        om += 0.5 * np.einsum("ijk,ijk->", ddg, M[12:].reshape(3, 3, 3))
+    return om
+
+
+def test_multipole_moments_equal_cartesian_and_converge(oracle):
+    """The harmonic form of the far field equals the paper's Cartesian order
+    0-2 expansion (independent moment computations) and converges to the
+    oracle's direct value as the order grows."""
+    P, _ = W.config3(grid=0)
+    P = P.subset(range(0, 4096, 29))
+    h = G.gwn_build3d(P, G.gwn_default_params(device=-1, max_diag_frac=10.0))
+    nodes = G.gwn_inspect(h, G.GWN_I_NODES)
+    M = G.gwn_inspect(h, G.GWN_I_MOMENTS)
+    MP = G.gwn_inspect(h, G.GWN_I_MULTIPOLE)
+    leaves = G.gwn_inspect(h, G.GWN_I_LEAVES)
+    G.gwn_free(h)
+
+    def subtree(i):
+        if nodes[i, 0]:
+            return [int(leaves[int(nodes[i, 1]), 0])]
+        return subtree(int(nodes[i, 1])) + subtree(int(nodes[i, 2]))
+    rng = W.Rng(71, "mpole")
+    checked = 0
+    for i in range(1, nodes.shape[0], 7):
+        if nodes[i, 0] or len(subtree(i)) < 3:
+            continue
+        c, r = nodes[i, 3:6], nodes[i, 6]
+        d = rng.uniform(3, -1, 1)
+        q = c + 5.0 * r * d / np.linalg.norm(d)
+        direct = 4 * math.pi * oracle.gwn3d(P.subset(subtree(i)), q[None])[0]
+        scale = max(abs(direct), np.abs(M[i][:3]).sum() / (5 * r) ** 2)
+        for p in range(3):
+            assert abs(multipole_omega(MP[i], q - c, p) - cartesian_omega(M[i], c - q, p)) < 1e-11 * scale, (i, p)
+        errs = [abs(multipole_omega(MP[i], q - c, p) - direct) for p in (0, 2, 4, 6)]
+        assert errs[3] <= errs[2] + 1e-9 * scale and errs[3] < 0.05 * errs[1] + 1e-9 * scale, (i, errs)
+        checked += 1
+        if checked == 6:
+            break
+    assert checked == 6
