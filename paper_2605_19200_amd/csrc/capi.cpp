@@ -414,8 +414,9 @@ extern "C" gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *
 {
     if (!h) return fail(GWN_EINVAL, "NULL handle");
     if (resident) *resident = h->m.arena_bytes + 256;
-    // keys + sort double buffer + permutation + reclass list + sort temp
-    if (per_query) *per_query = 8 + 8 + 4 + 4 + 16;   // keys x2, perm x2, sort temp
+    // keys x2, permutation x2, sort temp; 3D adds the near-field pass:
+    // partial sum, count, 64 leaf slots, flag (per query, rounded up)
+    if (per_query) *per_query = 8 + 8 + 4 + 4 + 16 + (h->m.dim == 3 ? 8 + 4 + 4 * 64 + 4 : 0);
     return GWN_OK;
 }
 

@@ -380,7 +380,7 @@ GWN_HD inline double foot_point3d(const double *__restrict__ h, double qx, doubl
 
 // Near-field solid angle of one (trimmed) patch at q.
 template <bool COUNT, class CtrT>
-GWN_HD inline double near3d(const QuadTables &Q, const Prim3 *__restrict__ P, const Trim3 *__restrict__ trims,
+GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, const Prim3 *__restrict__ P, const Trim3 *__restrict__ trims,
                             double qx, double qy, double qz, double eps_on, CtrT &ctr)
 {
     const double *__restrict__ h = P->h;

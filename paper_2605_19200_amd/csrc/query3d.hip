@@ -42,12 +42,24 @@ __constant__ QuadTables c_quad;
 
 __device__ __forceinline__ void ctr_add(Ctr &c, int k, long long v) { c.v[k] += v; }
 
-// Direct solid angle of one leaf at q (radians of solid angle).
+// Near-field leaves recorded per query by the traversal, in its DFS order
+// (at most kNearSlots; more sets the overflow flag and gives NaN).
+constexpr int kNearSlots = 64;
+
+struct NearScratch {
+    double *part;      // [n_waves * 64] solid angle of the far field and node-set leaves
+    int32_t *cnt;      // [n_waves * 64] near leaves met by the traversal
+    int32_t *list;     // [n_waves * 64 * kNearSlots] their node indices
+    uint8_t *need;     // [n_waves * 64] mixed form: lane re-evaluated in FP64
+};
+
+// Direct solid angle of one leaf at q by its precomputed node set, chosen by
+// distance / half-diagonal ratio (finest near, coarsest far).  A leaf within
+// near_ratio of its diagonal is recorded for the near-field pass instead.
 template <bool COUNT>
-__device__ double leaf3d(const DevModel &M, const Node3 *__restrict__ nd, double qx, double qy, double qz,
-                         bool active, Ctr &ctr)
+__device__ double leaf3d(const DevModel &M, const Node3 *__restrict__ nd, int cur, double qx, double qy, double qz,
+                         bool active, int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
-    const int leaf = -1 - nd->right;
     const double dx = fmax(fmax(nd->t[0] - qx, qx - nd->t[3]), 0.0);
     const double dy = fmax(fmax(nd->t[1] - qy, qy - nd->t[4]), 0.0);
     const double dz = fmax(fmax(nd->t[2] - qz, qz - nd->t[5]), 0.0);
@@ -56,8 +68,11 @@ __device__ double leaf3d(const DevModel &M, const Node3 *__restrict__ nd, double
     const bool near = d2 < M.near_ratio2 * diag2;
     double om = 0.0;
     if (COUNT && active) ctr.v[GWN_C_LEAVES]++;
+    if (active && near) {
+        if (ncnt < kNearSlots) mylist[ncnt] = cur;
+        ++ncnt;
+    }
     if (active && !near) {
-        // rule by distance / half-diagonal ratio (finest near, coarsest far)
         const double r2 = 4.0 * d2 / diag2;
         const int c0 = (int)nd->t[6], c1 = (int)nd->t[7], c2 = (int)nd->t[8];
         int off = 0, cnt = c0;
@@ -66,14 +81,11 @@ __device__ double leaf3d(const DevModel &M, const Node3 *__restrict__ nd, double
         const QNode3 *__restrict__ qn = (const QNode3 *)M.qnodes + nd->aux + off;
         for (int k = 0; k < cnt; ++k) {
             const double rx = qn[k].x[0] - qx, ry = qn[k].x[1] - qy, rz = qn[k].x[2] - qz;
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            const double inv = 1.0 / sqrt(r2);
+            const double rr = rx * rx + ry * ry + rz * rz;
+            const double inv = 1.0 / sqrt(rr);
             om += (qn[k].n[0] * rx + qn[k].n[1] * ry + qn[k].n[2] * rz) * (inv * inv * inv);
         }
         if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES] += cnt; }
-    }
-    if (active && near) {
-        om = near3d<COUNT>(c_quad, (const Prim3 *)M.prims + leaf, (const Trim3 *)M.trims, qx, qy, qz, M.eps_on, ctr);
     }
     return om;
 }
@@ -125,9 +137,11 @@ __device__ __forceinline__ T multipole3d(T sx, T sy, T sz, const T *__restrict__
     return omega;
 }
 
+// Traversal of one wave over a 3D model; returns the lane's solid angle of
+// the far field and the node-set leaves, and records its near leaves.
 template <bool F32, bool COUNT>
 __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz, uint64_t mask, StackLDS &S, int w,
-                             Ctr &ctr)
+                             int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
     const Node3 *__restrict__ nodes = (const Node3 *)M.nodes;
     const int lane = lane_id();
@@ -144,7 +158,7 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
         const int right = nd->right;
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            acc_leaf += leaf3d<COUNT>(M, nd, qx, qy, qz, active, ctr);
+            acc_leaf += leaf3d<COUNT>(M, nd, cur, qx, qy, qz, active, ncnt, mylist, ctr);
         } else {
             bool far = false;
             if (active) {
@@ -184,55 +198,145 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
         cur = uniform_i(S.node[w][sp]);
         curmask = uniform_u64(S.mask[w][sp]);
     }
-    return (acc_far + acc_leaf) * (1.0 / (4.0 * kPi));
+    return acc_far + acc_leaf;
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void k_query3d(LaunchTable T, const double *__restrict__ pts,
-                                                    const int32_t *__restrict__ perm, double *__restrict__ out_w,
-                                                    uint8_t *__restrict__ out_in, long long *counters)
+__device__ __forceinline__ int wave_segment(const LaunchTable &T, int wave)
+{
+    int lo = 0, hi = T.n_seg - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T.woff[mid] <= wave) lo = mid; else hi = mid - 1;
+    }
+    return uniform_i(lo);
+}
+
+// Pass 1 (3D): traversal of one wave of 64 sorted queries of one segment:
+// far field and node-set leaves, near leaves recorded.  RECLASS: only the
+// lanes flagged by the mixed form's first near pass, in FP64.
+template <bool COUNT, bool RECLASS>
+__global__ __launch_bounds__(kBlock) void k_trav3d(LaunchTable T, const double *__restrict__ pts,
+                                                   const int32_t *__restrict__ perm, NearScratch NS,
+                                                   long long *counters)
 {
     __shared__ StackLDS S;
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int wave = blockIdx.x * kWavesPerBlock + w;
     if (wave >= T.n_waves) return;
-    int s = 0;
-    {
-        int lo = 0, hi = T.n_seg - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (T.woff[mid] <= wave) lo = mid; else hi = mid - 1;
-        }
-        s = uniform_i(lo);
-    }
+    const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
     const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * 64 + lane;
+    const int64_t slot = (int64_t)wave * 64 + lane;
     const bool valid = pos < T.qoff[s + 1];
-    const int row = valid ? perm[pos] : 0;
-    const double qx = valid ? pts[3 * (int64_t)row] : 0.0;
-    const double qy = valid ? pts[3 * (int64_t)row + 1] : 0.0;
-    const double qz = valid ? pts[3 * (int64_t)row + 2] : 0.0;
-    const uint64_t mask = __ballot(valid);
+    const bool act = valid && (!RECLASS || NS.need[slot]);
+    const uint64_t mask = __ballot(act);
+    if (!mask) return;
+    const int row = act ? perm[pos] : 0;
+    const double qx = act ? pts[3 * (int64_t)row] : 0.0;
+    const double qy = act ? pts[3 * (int64_t)row + 1] : 0.0;
+    const double qz = act ? pts[3 * (int64_t)row + 2] : 0.0;
     Ctr ctr;
 #pragma unroll
     for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
-    double wq;
-    if (M.precision == GWN_MIXED) {
-        wq = traverse3d<true, COUNT>(M, qx, qy, qz, mask, S, w, ctr);
-        const bool need = valid && fabs(wq - 0.5) < M.band;
-        const uint64_t rmask = __ballot(need);
-        if (rmask) {
-            const double r = traverse3d<false, COUNT>(M, qx, qy, qz, rmask, S, w, ctr);
-            if (need) wq = r;
-            if (COUNT && need) ctr.v[GWN_C_RECLASS]++;
-        }
-    } else {
-        wq = traverse3d<false, COUNT>(M, qx, qy, qz, mask, S, w, ctr);
+    int ncnt = 0;
+    int32_t *mylist = NS.list + slot * kNearSlots;
+    double part;
+    if (!RECLASS && M.precision == GWN_MIXED)
+        part = traverse3d<true, COUNT>(M, qx, qy, qz, mask, S, w, ncnt, mylist, ctr);
+    else
+        part = traverse3d<false, COUNT>(M, qx, qy, qz, mask, S, w, ncnt, mylist, ctr);
+    if (act) {
+        NS.part[slot] = part;
+        NS.cnt[slot] = ncnt;
     }
-    if (valid) {
-        if (out_w) out_w[row] = wq;
-        if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
+    if (COUNT && RECLASS && act) ctr.v[GWN_C_RECLASS]++;
+    flush_counters<COUNT>(ctr, counters);
+}
+
+// Pass 2 (3D): the near-field leaves of one wave's queries, one (query,
+// leaf) pair per lane, then classification and scatter.  The pairs of the
+// wave are numbered query by query in the traversal's order; lane j of a
+// round of 64 takes pair base + j.  Each query then adds its pairs' values
+// one by one in that order, so its result does not depend on its wave or
+// batch mates.  Mixed form, first pass: lanes with |w - 0.5| < band are
+// flagged for the FP64 re-evaluation instead of written.
+template <bool COUNT, bool RECLASS>
+__global__ __launch_bounds__(kBlock) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
+                                                   const double *__restrict__ pts, double *__restrict__ out_w,
+                                                   uint8_t *__restrict__ out_in, long long *counters)
+{
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int wave = blockIdx.x * kWavesPerBlock + w;
+    if (wave >= T.n_waves) return;
+    const int s = wave_segment(T, wave);
+    const DevModel &M = T.models[T.seg_model[s]];
+    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * 64 + lane;
+    const int64_t slot = (int64_t)wave * 64 + lane;
+    const bool valid = pos < T.qoff[s + 1];
+    const bool act = valid && (!RECLASS || NS.need[slot]);
+    if (!__ballot(act)) return;
+    const int row = act ? perm[pos] : 0;
+    const double qx = act ? pts[3 * (int64_t)row] : 0.0;
+    const double qy = act ? pts[3 * (int64_t)row + 1] : 0.0;
+    const double qz = act ? pts[3 * (int64_t)row + 2] : 0.0;
+    const int full = act ? NS.cnt[slot] : 0;
+    const bool overflow = full > kNearSlots;
+    const int c = min(full, kNearSlots);
+    // inclusive prefix sum of the pair counts over the wave
+    int incl = c;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    const int excl = incl - c;
+    const int total = __shfl(incl, 63);
+    Ctr ctr;
+#pragma unroll
+    for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
+    double near_sum = 0.0;
+    for (int base = 0; base < total; base += 64) {
+        const int t = base + lane;
+        const bool has = t < total;
+        // owner: the first lane with incl > t, i.e. the number of lanes with
+        // incl <= t (incl is non-decreasing); the same six shuffles on every
+        // lane, so no lane reads from one that has left the search
+        int owner = 0;
+        for (int step = 32; step > 0; step >>= 1)
+            if (__shfl(incl, owner + step - 1) <= t) owner += step;
+        const int oexcl = __shfl(excl, owner);
+        const double ox = __shfl(qx, owner), oy = __shfl(qy, owner), oz = __shfl(qz, owner);
+        double v = 0.0;
+        if (has) {
+            const int node = NS.list[((int64_t)wave * 64 + owner) * kNearSlots + (t - oexcl)];
+            const Node3 *nd = (const Node3 *)M.nodes + node;
+            const int leaf = -1 - nd->right;
+            v = near3d<COUNT>(c_quad, (const Prim3 *)M.prims + leaf, (const Trim3 *)M.trims, ox, oy, oz, M.eps_on,
+                              ctr);
+        }
+        // this round holds pairs [max(excl, base), min(incl, base + 64)) of each lane
+        const int a = max(excl, base) - base, b = min(incl, base + 64) - base;
+        int span = b > a ? b - a : 0;
+        for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off));
+        for (int k = 0; k < span; ++k) {
+            const double x = __shfl(v, min(a + k, 63));
+            if (a + k < b) near_sum += x;
+        }
+    }
+    if (act) {
+        double wq = (NS.part[slot] + near_sum) * (1.0 / (4.0 * kPi));
+        if (overflow) {
+            wq = NAN;
+            atomicOr(M.flag, 1);
+            if (COUNT) ctr.v[GWN_C_OVERFLOW]++;
+        }
+        const bool band = !RECLASS && M.precision == GWN_MIXED && !overflow && fabs(wq - 0.5) < M.band;
+        if (!RECLASS) NS.need[slot] = band ? 1 : 0;
+        if (!band) {
+            if (out_w) out_w[row] = wq;
+            if (out_in) out_in[row] = wq >= 0.5 ? 1 : 0;
+        }
     }
     flush_counters<COUNT>(ctr, counters);
 }
@@ -265,15 +369,49 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
     }
     const int grid = (T.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
     if (grid == 0) return GWN_OK;
-    if (counters)
-        hipLaunchKernelGGL(k_query3d<true>, dim3(grid), dim3(kBlock), 0, stream, T, pts, perm, out_w, out_in,
-                           counters);
-    else
-        hipLaunchKernelGGL(k_query3d<false>, dim3(grid), dim3(kBlock), 0, stream, T, pts, perm, out_w, out_in,
-                           nullptr);
+    // per-slot scratch of the two passes (stream ordered)
+    const size_t ns = (size_t)T.n_waves * 64;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t b_part = al(ns * sizeof(double)), b_cnt = al(ns * sizeof(int32_t)),
+                 b_list = al(ns * kNearSlots * sizeof(int32_t)), b_need = al(ns);
+    char *buf = nullptr;
+    e = hipMallocAsync((void **)&buf, b_part + b_cnt + b_list + b_need, stream);
+    if (e != hipSuccess) {
+        err = std::string("hipMallocAsync near-field scratch: ") + hipGetErrorString(e);
+        return GWN_ENOMEM;
+    }
+    NearScratch NS;
+    NS.part = (double *)buf;
+    NS.cnt = (int32_t *)(buf + b_part);
+    NS.list = (int32_t *)(buf + b_part + b_cnt);
+    NS.need = (uint8_t *)(buf + b_part + b_cnt + b_list);
+    bool any_mixed = false;
+    for (int j = 0; j < T.n_seg; ++j) any_mixed |= T.models[T.seg_model[j]].precision == GWN_MIXED;
+    const dim3 g(grid), b(kBlock);
+    if (counters) {
+        hipLaunchKernelGGL((k_trav3d<true, false>), g, b, 0, stream, T, pts, perm, NS, counters);
+        hipLaunchKernelGGL((k_near3d<true, false>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+        if (any_mixed) {
+            hipLaunchKernelGGL((k_trav3d<true, true>), g, b, 0, stream, T, pts, perm, NS, counters);
+            hipLaunchKernelGGL((k_near3d<true, true>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+        }
+    } else {
+        hipLaunchKernelGGL((k_trav3d<false, false>), g, b, 0, stream, T, pts, perm, NS, counters);
+        hipLaunchKernelGGL((k_near3d<false, false>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+        if (any_mixed) {
+            hipLaunchKernelGGL((k_trav3d<false, true>), g, b, 0, stream, T, pts, perm, NS, counters);
+            hipLaunchKernelGGL((k_near3d<false, true>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in,
+                               counters);
+        }
+    }
     e = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(buf, stream);
     if (e != hipSuccess) {
         err = std::string("3D query launch: ") + hipGetErrorString(e);
+        return GWN_EHIP;
+    }
+    if (e2 != hipSuccess) {
+        err = std::string("hipFreeAsync near-field scratch: ") + hipGetErrorString(e2);
         return GWN_EHIP;
     }
     return GWN_OK;
