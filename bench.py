@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D side measurement")
+    ap.add_argument("--profile-3d", action="store_true",
+                    help="short run for rocprofv3: one FP64 and one mixed pass over the 3D bodies scene grid")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: 3 FP64 steps, then a 256 MiB device copy used to calibrate "
                          "FETCH_SIZE/WRITE_SIZE")
@@ -198,6 +200,9 @@ def main():
     from paper_2605_19200_amd import presets
     from paper_2605_19200_amd import workloads as W
 
+    if args.profile_3d:
+        print(json.dumps({"profile_3d": True, **bench3d()}))
+        return
     t_gen = time.time()
     curves, q = W.config2(grid=args.grid)
     n = q.shape[0]

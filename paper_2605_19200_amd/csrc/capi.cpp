@@ -94,10 +94,11 @@ void refresh_dev_params(Model &m)
     m.dev.gl_n = p.gl_nodes;
 }
 
-static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Prim2> &prims)
+static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> &hot, std::vector<Prim2> &prims)
 {
     const auto &T = m.tree.nodes;
     nodes.assign(T.size(), Node2{});
+    hot.assign(T.size(), Hot2{});
     for (size_t i = 0; i < T.size(); ++i) {
         const HostNode &h = T[i];
         Node2 &n = nodes[i];
@@ -119,6 +120,16 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Prim2>
         n.fc[1] = (float)n.c[1];
         n.fr2 = (float)n.r2;
         for (int k = 0; k < 2 * kMaxOrder2D; ++k) n.fm[k] = (float)n.m[k];
+        Hot2 &t = hot[i];
+        std::memset(&t, 0, sizeof t);
+        if (h.is_leaf) {
+            for (int k = 0; k < 4; ++k) t.a[k] = n.m[k];
+        } else {
+            t.a[0] = n.c[0]; t.a[1] = n.c[1]; t.a[2] = n.r2;
+        }
+        t.right = n.right;
+        t.degree = n.degree;
+        t.fc[0] = n.fc[0]; t.fc[1] = n.fc[1]; t.fr2 = n.fr2;
     }
     prims.assign(m.leaf_src.size(), Prim2{});
     for (size_t l = 0; l < prims.size(); ++l)
@@ -133,17 +144,18 @@ gwn_status upload_model(Model &m, std::string &err)
 {
     hipError_t e = hipSetDevice(m.device);
     if (e != hipSuccess) { err = std::string("hipSetDevice: ") + hipGetErrorString(e); return GWN_EHIP; }
-    // Arena: nodes | prims | trims | qnodes | mpole | fmpole, each 256-byte
-    // aligned (the last four are 3D only).
-    std::vector<Node2> n2; std::vector<Prim2> p2;
+    // Arena: nodes | prims | trims | qnodes | mpole | fmpole | hot, each
+    // 256-byte aligned (trims to fmpole are 3D only, hot 2D only).
+    std::vector<Node2> n2; std::vector<Prim2> p2; std::vector<Hot2> h2;
     std::vector<Node3> n3; std::vector<Prim3> p3;
     std::vector<float> fmp;
-    const void *src[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    size_t bytes[6] = {0, 0, 0, 0, 0, 0};
+    const void *src[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    size_t bytes[7] = {0, 0, 0, 0, 0, 0, 0};
     if (m.dim == 2) {
-        pack2d(m, n2, p2);
+        pack2d(m, n2, h2, p2);
         src[0] = n2.data(); bytes[0] = n2.size() * sizeof(Node2);
         src[1] = p2.data(); bytes[1] = p2.size() * sizeof(Prim2);
+        src[6] = h2.data(); bytes[6] = h2.size() * sizeof(Hot2);
     } else {
         pack3d(m, n3, p3);
         src[0] = n3.data(); bytes[0] = n3.size() * sizeof(Node3);
@@ -154,14 +166,14 @@ gwn_status upload_model(Model &m, std::string &err)
         src[4] = m.mpole.data(); bytes[4] = m.mpole.size() * sizeof(double);
         src[5] = fmp.data(); bytes[5] = fmp.size() * sizeof(float);
     }
-    size_t off[7];
+    size_t off[8];
     off[0] = 0;
-    for (int k = 0; k < 6; ++k) off[k + 1] = align_up(off[k] + bytes[k], 256);
-    size_t total = std::max<size_t>(off[6], 256);
+    for (int k = 0; k < 7; ++k) off[k + 1] = align_up(off[k] + bytes[k], 256);
+    size_t total = std::max<size_t>(off[7], 256);
     void *arena = nullptr;
     e = hipMalloc(&arena, total);
     if (e != hipSuccess) { err = std::string("hipMalloc arena: ") + hipGetErrorString(e); return GWN_ENOMEM; }
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 7; ++k)
         if (bytes[k]) {
             e = hipMemcpy((char *)arena + off[k], src[k], bytes[k], hipMemcpyHostToDevice);
             if (e != hipSuccess) {
@@ -196,6 +208,7 @@ gwn_status upload_model(Model &m, std::string &err)
     m.dev.qnodes = (char *)arena + off[3];
     m.dev.mpole = (char *)arena + off[4];
     m.dev.fmpole = (char *)arena + off[5];
+    m.dev.hot = (char *)arena + off[6];
     m.dev.flag = flag;
     m.dev.n_nodes = (int32_t)m.tree.nodes.size();
     refresh_dev_params(m);

@@ -45,6 +45,23 @@ struct alignas(128) Node2 {
 };
 static_assert(sizeof(Node2) == 256, "Node2 must be two 128-byte lines");
 
+// 2D traversal record, 64 bytes, one array of them beside the Node2 array
+// (same DFS index).  It holds everything a node test or a leaf's fast path
+// reads, so the traversal's working set stays small enough for each XCD's
+// L2: internal nodes a = (c.x, c.y, r^2, 0) with the FP32 copies, leaves
+// a = control-point AABB (lo.x, lo.y, hi.x, hi.y); `right` and `degree` as
+// in Node2.  The moments stay in Node2 and are read for accepted clusters
+// only.
+struct alignas(64) Hot2 {
+    double a[4];
+    int32_t right;
+    int32_t degree;
+    float fc[2];
+    float fr2;
+    float pad[3];
+};
+static_assert(sizeof(Hot2) == 64, "Hot2 must be 64 bytes");
+
 // 2D leaf primitive: homogeneous cubic control points (w x, w y, w) x 4.
 struct Prim2 {
     double h[12];
@@ -113,6 +130,7 @@ struct QNode3 {
 // ---------------------------------------------------------------------------
 struct DevModel {
     const void *nodes;      // Node2* or Node3*
+    const void *hot;        // Hot2* (2D)
     const void *prims;      // Prim2* or Prim3*
     const void *trims;      // Trim3* (3D)
     const void *qnodes;     // QNode3* (3D)

@@ -183,7 +183,7 @@ __device__ __forceinline__ double lerp_exact(double a, double b, double t, doubl
 // The end point of each piece is carried to the next so consecutive chords
 // share their end points bit for bit.
 template <bool COUNT>
-__device__ void leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__ prims, double qx, double qy,
+__device__ void leaf2d(const Hot2 *__restrict__ nd, const Prim2 *__restrict__ prims, double qx, double qy,
                        double eps_on, AngleAcc &A, Ctr &ctr, bool &overflow)
 {
     const int leaf = -1 - nd->right;
@@ -196,7 +196,7 @@ __device__ void leaf2d(const Node2 *__restrict__ nd, const Prim2 *__restrict__ p
         by[i] = fma(-qy, w, P->h[3 * i + 1]);
     }
     if (COUNT) ctr.v[GWN_C_LEAVES]++;
-    const bool outside = qx < nd->m[0] || qy < nd->m[1] || qx > nd->m[2] || qy > nd->m[3];
+    const bool outside = qx < nd->a[0] || qy < nd->a[1] || qx > nd->a[2] || qy > nd->a[3];
     if (outside || nd->degree == 1) {
         if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
         angle_add_chord(A, bx[0] * by[3] - by[0] * bx[3], bx[0] * bx[3] + by[0] * by[3]);
@@ -299,6 +299,7 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                              Ctr &ctr, bool &overflow)
 {
     const Node2 *__restrict__ nodes = (const Node2 *)M.nodes;
+    const Hot2 *__restrict__ hot = (const Hot2 *)M.hot;
     const Prim2 *__restrict__ prims = (const Prim2 *)M.prims;
     const int lane = lane_id();
     const bool me = (mask >> lane) & 1;
@@ -313,25 +314,26 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     int sp = 0;
     if (M.n_nodes == 0) return 0.0;
     while (true) {
-        const Node2 *nd = nodes + cur;
-        const int right = nd->right;
+        const Hot2 *hd = hot + cur;
+        const int right = hd->right;
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            if (active) leaf2d<COUNT>(nd, prims, qx, qy, M.eps_on, A, ctr, overflow);
+            if (active) leaf2d<COUNT>(hd, prims, qx, qy, M.eps_on, A, ctr, overflow);
         } else {
             bool far = false;
             if (active) {
                 if (COUNT) ctr.v[GWN_C_NODES]++;
                 if (F32) {
-                    const float dx = qxf - nd->fc[0], dy = qyf - nd->fc[1];
+                    const float dx = qxf - hd->fc[0], dy = qyf - hd->fc[1];
                     const float d2 = dx * dx + dy * dy;
-                    far = d2 > beta2f * nd->fr2;
-                    if (far) acc += (double)taylor2d<float>(dx, dy, d2, nd->fm, min(M.order, kMaxOrder2D - 1));
+                    far = d2 > beta2f * hd->fr2;
+                    if (far)
+                        acc += (double)taylor2d<float>(dx, dy, d2, nodes[cur].fm, min(M.order, kMaxOrder2D - 1));
                 } else {
-                    const double dx = qx - nd->c[0], dy = qy - nd->c[1];
+                    const double dx = qx - hd->a[0], dy = qy - hd->a[1];
                     const double d2 = dx * dx + dy * dy;
-                    far = d2 > beta2 * nd->r2;
-                    if (far) acc += taylor2d<double>(dx, dy, d2, nd->m, M.order);
+                    far = d2 > beta2 * hd->a[2];
+                    if (far) acc += taylor2d<double>(dx, dy, d2, nodes[cur].m, M.order);
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }
