@@ -177,8 +177,10 @@ GWN_HD inline double radial(const QuadTables &Q, const double *__restrict__ h, d
             const double a = cuts[piece], b = cuts[piece + 1];
             for (int i = 0; i < kRadialGL; ++i) {
                 const double ms = mu * (a + (b - a) * Q.gx12[i]);
-                const double tau = eps * sinh(ms);
-                const double dtau = eps * mu * cosh(ms) * (b - a) * Q.gw12[i];
+                // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
+                const double em = expm1(ms), ie = 1.0 / (1.0 + em);
+                const double tau = eps * 0.5 * (em + em * ie);
+                const double dtau = eps * mu * 0.5 * (1.0 + em + ie) * (b - a) * Q.gw12[i];
                 HomEval e;
                 hom_eval(h, cu + tau * ru, cv + tau * rv, qx, qy, qz, e);
                 sum += dtau * tau * density(e);
@@ -190,14 +192,14 @@ GWN_HD inline double radial(const QuadTables &Q, const double *__restrict__ h, d
 }
 
 // Geometric panels on [a, b] graded from `c` (in [a, b]) with first width
-// min(h0, 1/8), each integrated with the outer Gauss-Legendre rule.
+// h0, each integrated with the outer Gauss-Legendre rule.
 template <class F>
 GWN_HD inline double graded_panels(const QuadTables &Q, double a, double b, double c, double h0, F &&f)
 {
     double total = 0.0;
     for (int side = 0; side < 2; ++side) {
         const double end = side == 0 ? b : a;
-        double lo = c, w = fmin(h0, 0.125);
+        double lo = c, w = h0;
         for (int k = 0; k < kMaxPanelsSide; ++k) {
             if (side == 0 ? lo >= end : lo <= end) break;
             double hi = side == 0 ? fmin(end, lo + w) : fmax(end, lo - w);
@@ -312,7 +314,9 @@ GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__res
     for (int k = 0; k < nc; ++k) {
         const double lo = k == 0 ? 0.0 : 0.5 * (centres[k - 1] + centres[k]);
         const double hi = k == nc - 1 ? 1.0 : 0.5 * (centres[k] + centres[k + 1]);
-        total += graded_panels(Q, lo, hi, centres[k], widths[k], integrand);
+        // first panel at most 1/4 of the curve; 1/8 at a collapsed edge
+        // (pole), where the integrand is near-singular along the whole edge
+        total += graded_panels(Q, lo, hi, centres[k], fmin(widths[k], fr.anis < 0.2 ? 0.125 : 0.25), integrand);
     }
     return total;
 }
