@@ -294,6 +294,7 @@ def main():
     mismm = int(np.sum(((wm[acc_idx] >= 0.5) != (ref >= 0.5)) & sure))
 
     served = None if args.no_served else served_benchmark()
+    served_all = None if args.no_served else served_benchmark(n_requests=200, kinds=("2d", "3d"), exp3d=(3.0, 4.0))
     side3d = None if args.no_3d else bench3d()
 
     cpu = None
@@ -337,6 +338,7 @@ def main():
                   "reclassified": int(cm["reclass"]), "ms_per_step": (tm1 - tm0) / args.steps * 1e3,
                   "counters": cm},
         "served": served,
+        "served_2d_3d": served_all,
         "3d": side3d,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,

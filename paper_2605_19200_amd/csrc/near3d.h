@@ -322,9 +322,11 @@ GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__res
 }
 
 // Foot point of q on the untrimmed patch: 9 x 9 samples, then projected
-// Gauss-Newton steps with step halving from the two best samples (the
-// distance can have several local minima on strongly non-uniform patches).
-// Returns the squared distance; (u, v) the parameters, Su / Sv the partials.
+// Gauss-Newton steps with step halving from the best sample and from the
+// best one away from it (the distance can have several local minima on
+// strongly non-uniform or folded patches).
+// Returns the squared distance; (u, v) the parameters, Su / Sv the partials;
+// (ou, ov, od) the other converged minimum (possibly the same point).
 GWN_HD inline double gauss_newton_foot(const double *__restrict__ h, double qx, double qy, double qz, double &bu,
                                        double &bv, double bd)
 {
@@ -358,23 +360,36 @@ GWN_HD inline double gauss_newton_foot(const double *__restrict__ h, double qx, 
 }
 
 GWN_HD inline double foot_point3d(const double *__restrict__ h, double qx, double qy, double qz, double &bu,
-                                  double &bv, double Su[3], double Sv[3])
+                                  double &bv, double Su[3], double Sv[3], double &ou, double &ov, double &od)
 {
+    // best sample, then the best one outside its 5 x 5 neighbourhood (a
+    // start in another basin when the distance has a second minimum)
     double d1 = INFINITY, d2b = INFINITY, u1 = 0.5, v1 = 0.5, u2 = 0.5, v2 = 0.5;
+    int i1 = 0, j1 = 0;
     for (int i = 0; i <= 8; ++i)
         for (int j = 0; j <= 8; ++j) {
             HomEval e;
             hom_eval(h, 0.125 * i, 0.125 * j, qx, qy, qz, e);
             const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
-            if (d2 < d1) { d2b = d1; u2 = u1; v2 = v1; d1 = d2; u1 = 0.125 * i; v1 = 0.125 * j; }
-            else if (d2 < d2b) { d2b = d2; u2 = 0.125 * i; v2 = 0.125 * j; }
+            if (d2 < d1) { d1 = d2; u1 = 0.125 * i; v1 = 0.125 * j; i1 = i; j1 = j; }
+        }
+    for (int i = 0; i <= 8; ++i)
+        for (int j = 0; j <= 8; ++j) {
+            if (abs(i - i1) <= 2 && abs(j - j1) <= 2) continue;
+            HomEval e;
+            hom_eval(h, 0.125 * i, 0.125 * j, qx, qy, qz, e);
+            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
+            if (d2 < d2b) { d2b = d2; u2 = 0.125 * i; v2 = 0.125 * j; }
         }
     d1 = gauss_newton_foot(h, qx, qy, qz, u1, v1, d1);
     if (d2b < INFINITY) d2b = gauss_newton_foot(h, qx, qy, qz, u2, v2, d2b);
     double bd = d1;
     bu = u1;
     bv = v1;
-    if (d2b < d1) { bd = d2b; bu = u2; bv = v2; }
+    ou = u2;
+    ov = v2;
+    od = d2b;
+    if (d2b < d1) { bd = d2b; bu = u2; bv = v2; ou = u1; ov = v1; od = d1; }
     double r[3];
     HomEval e;
     hom_eval(h, bu, bv, qx, qy, qz, e);
@@ -382,25 +397,25 @@ GWN_HD inline double foot_point3d(const double *__restrict__ h, double qx, doubl
     return bd;
 }
 
-// Near-field solid angle of one (trimmed) patch at q.
-template <bool COUNT, class CtrT>
-GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, const Prim3 *__restrict__ P, const Trim3 *__restrict__ trims,
-                            double qx, double qy, double qz, double eps_on, CtrT &ctr)
+// Polar frame at the foot point (cu, cv) with squared distance d2.
+GWN_HD inline NearFrame near_frame(const double *__restrict__ h, double cu, double cv, double d2, double qx,
+                                   double qy, double qz, double eps_on)
 {
-    const double *__restrict__ h = P->h;
-    double bu, bv, Su[3], Sv[3];
-    const double bd = foot_point3d(h, qx, qy, qz, bu, bv, Su, Sv);
+    NearFrame fr;
+    fr.cu = cu;
+    fr.cv = cv;
+    double r[3];
+    HomEval e;
+    hom_eval(h, cu, cv, qx, qy, qz, e);
+    euclid(e, r, fr.Su, fr.Sv);
     // q on the surface (within eps_on): no near-singular peak is resolved,
     // which yields the direct value (mean of the one-sided limits)
-    NearFrame fr;
-    fr.cu = bu;
-    fr.cv = bv;
-    const bool on_surface = sqrt(bd) < eps_on;
-    fr.dist = on_surface ? 1e300 : sqrt(bd);
-    for (int k = 0; k < 3; ++k) { fr.Su[k] = Su[k]; fr.Sv[k] = Sv[k]; }
+    const bool on_surface = sqrt(d2) < eps_on;
+    fr.dist = on_surface ? 1e300 : sqrt(d2);
     // metric J^T J at c: eigenvalues l1 <= l2; weak direction perpendicular
     // to the major axis at angle atan2(2 gb, ga - gc) / 2 (stable also when
     // gb is pure roundoff)
+    const double *Su = fr.Su, *Sv = fr.Sv;
     const double ga = Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2];
     const double gb = Su[0] * Sv[0] + Su[1] * Sv[1] + Su[2] * Sv[2];
     const double gc = Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2];
@@ -410,15 +425,71 @@ GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, 
     fr.ew_u = -sin(theta);
     fr.ew_v = cos(theta);
     fr.anis = l2 > 0.0 ? sqrt(l1 / l2) : 1.0;
-    fr.dparam = l2 > 0.0 ? fmax(sqrt(bd), eps_on) / sqrt(l2) : 1.0;
+    fr.dparam = l2 > 0.0 ? fmax(sqrt(d2), eps_on) / sqrt(l2) : 1.0;
+    return fr;
+}
+
+// Straight edge e (0..3, counter-clockwise) of [u0, u1] x [v0, v1].
+GWN_HD inline Curve2 rect_edge(double u0, double u1, double v0, double v1, int e)
+{
+    const double P[5][2] = {{u0, v0}, {u1, v0}, {u1, v1}, {u0, v1}, {u0, v0}};
+    Curve2 c;
+    c.h[0] = P[e][0]; c.h[1] = P[e][1]; c.h[2] = 1.0;
+    c.h[3] = 0.5 * (P[e][0] + P[e + 1][0]); c.h[4] = 0.5 * (P[e][1] + P[e + 1][1]); c.h[5] = 1.0;
+    c.h[6] = P[e + 1][0]; c.h[7] = P[e + 1][1]; c.h[8] = 1.0;
+    return c;
+}
+
+// Near-field solid angle of one (trimmed) patch at q.  When the distance to
+// an untrimmed patch has a second local minimum (a fold, or a strongly
+// non-uniform parametrisation that stretches the near-singular region) no
+// farther from q than twice the two minima's separation on the surface, the
+// patch is split halfway between them into two rectangles, each integrated
+// about its own foot point: the rule resolves one near-singular peak per
+// domain.
+template <bool COUNT, class CtrT>
+GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, const Prim3 *__restrict__ P,
+                                                           const Trim3 *__restrict__ trims, double qx, double qy,
+                                                           double qz, double eps_on, CtrT &ctr)
+{
+    const double *__restrict__ h = P->h;
+    double bu, bv, Su[3], Sv[3], ou, ov, od;
+    const double bd = foot_point3d(h, qx, qy, qz, bu, bv, Su, Sv, ou, ov, od);
     double total = 0.0;
     const int nt = P->trim_count;
     if (nt == 0) {
-        for (int e = 0; e < 4; ++e) {
-            const Curve2 cv = square_edge(e);
-            total += curve_contribution(Q, h, cv, fr, qx, qy, qz, ctr, COUNT);
+        bool split = false;
+        if (fabs(ou - bu) + fabs(ov - bv) > 0.05 && od < INFINITY) {
+            HomEval e1, e2;
+            hom_eval(h, bu, bv, qx, qy, qz, e1);
+            hom_eval(h, ou, ov, qx, qy, qz, e2);
+            double sep2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double d = e1.A[k] / e1.W - e2.A[k] / e2.W;
+                sep2 += d * d;
+            }
+            split = od < 4.0 * sep2;
+        }
+        if (!split) {
+            const NearFrame fr = near_frame(h, bu, bv, bd, qx, qy, qz, eps_on);
+            for (int e = 0; e < 4; ++e)
+                total += curve_contribution(Q, h, square_edge(e), fr, qx, qy, qz, ctr, COUNT);
+        } else {
+            // cut across the larger parameter gap, halfway between the minima
+            const bool cut_u = fabs(ou - bu) >= fabs(ov - bv);
+            const double cut = cut_u ? 0.5 * (bu + ou) : 0.5 * (bv + ov);
+            for (int part = 0; part < 2; ++part) {
+                const double cu = part ? ou : bu, cv = part ? ov : bv, d2 = part ? od : bd;
+                const bool low = (cut_u ? cu : cv) < cut;
+                const double u0 = cut_u ? (low ? 0.0 : cut) : 0.0, u1 = cut_u ? (low ? cut : 1.0) : 1.0;
+                const double v0 = cut_u ? 0.0 : (low ? 0.0 : cut), v1 = cut_u ? 1.0 : (low ? cut : 1.0);
+                const NearFrame fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
+                for (int e = 0; e < 4; ++e)
+                    total += curve_contribution(Q, h, rect_edge(u0, u1, v0, v1, e), fr, qx, qy, qz, ctr, COUNT);
+            }
         }
     } else {
+        const NearFrame fr = near_frame(h, bu, bv, bd, qx, qy, qz, eps_on);
         for (int k = 0; k < nt; ++k) {
             Curve2 cv;
             const Trim3 *t = trims + P->trim_begin + k;

@@ -196,3 +196,15 @@ def test_paper_order_3d(cfg3):
     m = G.Model(P, presets.params(presets.PAPER_ORDER_3D))
     w, ins = run(m, qs)
     check(w, ins, ref)
+
+
+def test_stretched_patch_near_field(cfg3, oracle):
+    """A query 1.4e-4 from a bodies-scene patch whose distance function has a
+    second local minimum 4.9e-3 away (strongly non-uniform parametrisation
+    near a pole): the near-field rule splits the patch between the minima."""
+    P = cfg3[0]
+    q = np.array([[-0.1256628870943714, 2.3888418271647667, 3.493370704897016]])
+    q = np.concatenate([q, q + np.array([[2e-4, -1e-4, 5e-5]]), q + np.array([[-3e-4, 2e-4, 1e-4]])])
+    m = G.Model(P, presets.params(presets.FP64_3D))
+    w, ins = run(m, q)
+    check(w, ins, oracle.gwn3d(P, q))
