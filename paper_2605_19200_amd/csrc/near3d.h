@@ -153,41 +153,46 @@ GWN_HD inline double radial(const QuadTables &Q, const double *__restrict__ h, d
     const double lx = Su[0] * ru + Sv[0] * rv, ly = Su[1] * ru + Sv[1] * rv, lz = Su[2] * ru + Sv[2] * rv;
     const double L = sqrt(lx * lx + ly * ly + lz * lz);
     const double eps = L > 0.0 ? dist / L : 1.0;
-    double sum = 0.0;
-    if (eps >= 0.5) {
-        for (int half = 0; half < 2; ++half)
-            for (int i = 0; i < kRadialGL; ++i) {
-                const double tau = 0.5 * (half + Q.gx12[i]);
-                HomEval e;
-                hom_eval(h, cu + tau * ru, cv + tau * rv, qx, qy, qz, e);
-                sum += 0.5 * Q.gw12[i] * tau * density(e);
-            }
-        if (count) ctr_add(ctr, GWN_C_PIECES, 2 * kRadialGL);
-    } else {
-        // pieces in sigma: tau <= 4 eps, 4 eps <= tau <= 0.1, tau >= 0.1
-        // (fewer when eps is not small; no piece may reach past tau = 1,
-        // where the patch is evaluated outside its parameter square)
-        const double mu = asinh(1.0 / eps);
+    // eps >= 0.5: two uniform Gauss-Legendre pieces in tau.  Otherwise
+    // pieces in sigma with tau = eps sinh(mu sigma): tau <= 4 eps,
+    // 4 eps <= tau <= 0.1, tau >= 0.1 (fewer when eps is not small; no piece
+    // may reach past tau = 1, where the patch is evaluated outside its
+    // parameter square).  One loop, so the patch evaluation is inlined once.
+    const bool uni = eps >= 0.5;
+    double mu = 1.0, cuts[4] = {0.0, 0.5, 1.0, 1.0};
+    int npieces = 2;
+    if (!uni) {
+        mu = asinh(1.0 / eps);
         const double sa = asinh(4.0) / mu, sb = asinh(0.1 / eps) / mu;
-        double cuts[4] = {0.0, 1.0, 1.0, 1.0};
-        int npieces = 1;
+        npieces = 1;
+        cuts[1] = 1.0;
+        cuts[2] = 1.0;
         if (sb > sa) { cuts[1] = sa; cuts[2] = sb; npieces = 3; }
         else if (sa < 1.0) { cuts[1] = sa; npieces = 2; }
-        for (int piece = 0; piece < npieces; ++piece) {
-            const double a = cuts[piece], b = cuts[piece + 1];
-            for (int i = 0; i < kRadialGL; ++i) {
-                const double ms = mu * (a + (b - a) * Q.gx12[i]);
-                // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
-                const double em = expm1(ms), ie = 1.0 / (1.0 + em);
-                const double tau = eps * 0.5 * (em + em * ie);
-                const double dtau = eps * mu * 0.5 * (1.0 + em + ie) * (b - a) * Q.gw12[i];
-                HomEval e;
-                hom_eval(h, cu + tau * ru, cv + tau * rv, qx, qy, qz, e);
-                sum += dtau * tau * density(e);
-            }
-        }
-        if (count) ctr_add(ctr, GWN_C_PIECES, npieces * kRadialGL);
     }
+    double sum = 0.0;
+#pragma unroll 1
+    for (int piece = 0; piece < npieces; ++piece) {
+        const double a = cuts[piece], b = cuts[piece + 1];
+#pragma unroll 1
+        for (int i = 0; i < kRadialGL; ++i) {
+            const double x = a + (b - a) * Q.gx12[i];
+            double tau, wt;
+            if (uni) {
+                tau = x;
+                wt = (b - a) * Q.gw12[i];
+            } else {
+                // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
+                const double em = expm1(mu * x), ie = 1.0 / (1.0 + em);
+                tau = eps * 0.5 * (em + em * ie);
+                wt = eps * mu * 0.5 * (1.0 + em + ie) * (b - a) * Q.gw12[i];
+            }
+            HomEval e;
+            hom_eval(h, cu + tau * ru, cv + tau * rv, qx, qy, qz, e);
+            sum += wt * tau * density(e);
+        }
+    }
+    if (count) ctr_add(ctr, GWN_C_PIECES, npieces * kRadialGL);
     return sum;
 }
 
@@ -455,47 +460,45 @@ GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, 
     const double *__restrict__ h = P->h;
     double bu, bv, Su[3], Sv[3], ou, ov, od;
     const double bd = foot_point3d(h, qx, qy, qz, bu, bv, Su, Sv, ou, ov, od);
-    double total = 0.0;
     const int nt = P->trim_count;
-    if (nt == 0) {
-        bool split = false;
-        if (fabs(ou - bu) + fabs(ov - bv) > 0.05 && od < INFINITY) {
-            HomEval e1, e2;
-            hom_eval(h, bu, bv, qx, qy, qz, e1);
-            hom_eval(h, ou, ov, qx, qy, qz, e2);
-            double sep2 = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                const double d = e1.A[k] / e1.W - e2.A[k] / e2.W;
-                sep2 += d * d;
-            }
-            split = od < 4.0 * sep2;
+    bool split = false;
+    if (nt == 0 && fabs(ou - bu) + fabs(ov - bv) > 0.05 && od < INFINITY) {
+        HomEval e1, e2;
+        hom_eval(h, bu, bv, qx, qy, qz, e1);
+        hom_eval(h, ou, ov, qx, qy, qz, e2);
+        double sep2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double d = e1.A[k] / e1.W - e2.A[k] / e2.W;
+            sep2 += d * d;
         }
-        if (!split) {
-            const NearFrame fr = near_frame(h, bu, bv, bd, qx, qy, qz, eps_on);
-            for (int e = 0; e < 4; ++e)
-                total += curve_contribution(Q, h, square_edge(e), fr, qx, qy, qz, ctr, COUNT);
-        } else {
-            // cut across the larger parameter gap, halfway between the minima
-            const bool cut_u = fabs(ou - bu) >= fabs(ov - bv);
-            const double cut = cut_u ? 0.5 * (bu + ou) : 0.5 * (bv + ov);
-            for (int part = 0; part < 2; ++part) {
-                const double cu = part ? ou : bu, cv = part ? ov : bv, d2 = part ? od : bd;
-                const bool low = (cut_u ? cu : cv) < cut;
-                const double u0 = cut_u ? (low ? 0.0 : cut) : 0.0, u1 = cut_u ? (low ? cut : 1.0) : 1.0;
-                const double v0 = cut_u ? 0.0 : (low ? 0.0 : cut), v1 = cut_u ? 1.0 : (low ? cut : 1.0);
-                const NearFrame fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
-                for (int e = 0; e < 4; ++e)
-                    total += curve_contribution(Q, h, rect_edge(u0, u1, v0, v1, e), fr, qx, qy, qz, ctr, COUNT);
-            }
+        split = od < 4.0 * sep2;
+    }
+    // cut across the larger parameter gap, halfway between the minima
+    const bool cut_u = fabs(ou - bu) >= fabs(ov - bv);
+    const double cut = cut_u ? 0.5 * (bu + ou) : 0.5 * (bv + ov);
+    double total = 0.0;
+    const int nparts = split ? 2 : 1;
+#pragma unroll 1
+    for (int part = 0; part < nparts; ++part) {
+        const double cu = part ? ou : bu, cv = part ? ov : bv, d2 = part ? od : bd;
+        double u0 = 0.0, u1 = 1.0, v0 = 0.0, v1 = 1.0;
+        if (split) {
+            const bool low = (cut_u ? cu : cv) < cut;
+            if (cut_u) { if (low) u1 = cut; else u0 = cut; }
+            else { if (low) v1 = cut; else v0 = cut; }
         }
-    } else {
-        const NearFrame fr = near_frame(h, bu, bv, bd, qx, qy, qz, eps_on);
-        for (int k = 0; k < nt; ++k) {
-            Curve2 cv;
-            const Trim3 *t = trims + P->trim_begin + k;
-#pragma unroll
-            for (int m = 0; m < 9; ++m) cv.h[m] = t->h[m];
-            total += curve_contribution(Q, h, cv, fr, qx, qy, qz, ctr, COUNT);
+        const NearFrame fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
+        const int ncv = nt == 0 ? 4 : nt;
+#pragma unroll 1
+        for (int k = 0; k < ncv; ++k) {
+            Curve2 crv;
+            if (nt == 0) {
+                crv = rect_edge(u0, u1, v0, v1, k);
+            } else {
+                const Trim3 *t = trims + P->trim_begin + k;
+                for (int m = 0; m < 9; ++m) crv.h[m] = t->h[m];
+            }
+            total += curve_contribution(Q, h, crv, fr, qx, qy, qz, ctr, COUNT);
         }
     }
     return total;
