@@ -330,8 +330,8 @@ GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__res
 // Gauss-Newton steps with step halving from the best sample and from the
 // best one away from it (the distance can have several local minima on
 // strongly non-uniform or folded patches).
-// Returns the squared distance; (u, v) the parameters, Su / Sv the partials;
-// (ou, ov, od) the other converged minimum (possibly the same point).
+// Returns the squared distance and (u, v) the parameters; (ou, ov, od) the
+// other converged minimum (possibly the same point).
 GWN_HD inline double gauss_newton_foot(const double *__restrict__ h, double qx, double qy, double qz, double &bu,
                                        double &bv, double bd)
 {
@@ -365,29 +365,30 @@ GWN_HD inline double gauss_newton_foot(const double *__restrict__ h, double qx, 
 }
 
 GWN_HD inline double foot_point3d(const double *__restrict__ h, double qx, double qy, double qz, double &bu,
-                                  double &bv, double Su[3], double Sv[3], double &ou, double &ov, double &od)
+                                  double &bv, double &ou, double &ov, double &od)
 {
     // best sample, then the best one outside its 5 x 5 neighbourhood (a
-    // start in another basin when the distance has a second minimum)
+    // start in another basin when the distance has a second minimum); one
+    // loop over both passes, so the patch evaluation is inlined once
     double d1 = INFINITY, d2b = INFINITY, u1 = 0.5, v1 = 0.5, u2 = 0.5, v2 = 0.5;
     int i1 = 0, j1 = 0;
-    for (int i = 0; i <= 8; ++i)
-        for (int j = 0; j <= 8; ++j) {
-            HomEval e;
-            hom_eval(h, 0.125 * i, 0.125 * j, qx, qy, qz, e);
-            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
-            if (d2 < d1) { d1 = d2; u1 = 0.125 * i; v1 = 0.125 * j; i1 = i; j1 = j; }
-        }
-    for (int i = 0; i <= 8; ++i)
-        for (int j = 0; j <= 8; ++j) {
-            if (abs(i - i1) <= 2 && abs(j - j1) <= 2) continue;
-            HomEval e;
-            hom_eval(h, 0.125 * i, 0.125 * j, qx, qy, qz, e);
-            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
-            if (d2 < d2b) { d2b = d2; u2 = 0.125 * i; v2 = 0.125 * j; }
-        }
-    d1 = gauss_newton_foot(h, qx, qy, qz, u1, v1, d1);
-    if (d2b < INFINITY) d2b = gauss_newton_foot(h, qx, qy, qz, u2, v2, d2b);
+#pragma unroll 1
+    for (int t = 0; t < 162; ++t) {
+        const bool second = t >= 81;
+        const int k = second ? t - 81 : t, i = k / 9, j = k - 9 * (k / 9);
+        if (second && abs(i - i1) <= 2 && abs(j - j1) <= 2) continue;
+        HomEval e;
+        hom_eval(h, 0.125 * i, 0.125 * j, qx, qy, qz, e);
+        const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
+        if (!second && d2 < d1) { d1 = d2; u1 = 0.125 * i; v1 = 0.125 * j; i1 = i; j1 = j; }
+        if (second && d2 < d2b) { d2b = d2; u2 = 0.125 * i; v2 = 0.125 * j; }
+    }
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {
+        double u = k ? u2 : u1, v = k ? v2 : v1, d = k ? d2b : d1;
+        if (d < INFINITY) d = gauss_newton_foot(h, qx, qy, qz, u, v, d);
+        if (k) { u2 = u; v2 = v; d2b = d; } else { u1 = u; v1 = v; d1 = d; }
+    }
     double bd = d1;
     bu = u1;
     bv = v1;
@@ -395,10 +396,6 @@ GWN_HD inline double foot_point3d(const double *__restrict__ h, double qx, doubl
     ov = v2;
     od = d2b;
     if (d2b < d1) { bd = d2b; bu = u2; bv = v2; ou = u1; ov = v1; od = d1; }
-    double r[3];
-    HomEval e;
-    hom_eval(h, bu, bv, qx, qy, qz, e);
-    euclid(e, r, Su, Sv);
     return bd;
 }
 
@@ -458,18 +455,20 @@ GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, 
                                                            double qz, double eps_on, CtrT &ctr)
 {
     const double *__restrict__ h = P->h;
-    double bu, bv, Su[3], Sv[3], ou, ov, od;
-    const double bd = foot_point3d(h, qx, qy, qz, bu, bv, Su, Sv, ou, ov, od);
+    double bu, bv, ou, ov, od;
+    const double bd = foot_point3d(h, qx, qy, qz, bu, bv, ou, ov, od);
     const int nt = P->trim_count;
     bool split = false;
     if (nt == 0 && fabs(ou - bu) + fabs(ov - bv) > 0.05 && od < INFINITY) {
-        HomEval e1, e2;
-        hom_eval(h, bu, bv, qx, qy, qz, e1);
-        hom_eval(h, ou, ov, qx, qy, qz, e2);
-        double sep2 = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            const double d = e1.A[k] / e1.W - e2.A[k] / e2.W;
-            sep2 += d * d;
+        double p[3] = {0.0, 0.0, 0.0}, sep2 = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < 2; ++k) {
+            HomEval e;
+            hom_eval(h, k ? ou : bu, k ? ov : bv, qx, qy, qz, e);
+            for (int a = 0; a < 3; ++a) {
+                const double x = e.A[a] / e.W;
+                if (k) sep2 += (x - p[a]) * (x - p[a]); else p[a] = x;
+            }
         }
         split = od < 4.0 * sep2;
     }
