@@ -183,8 +183,8 @@ __device__ __forceinline__ double lerp_exact(double a, double b, double t, doubl
 // The end point of each piece is carried to the next so consecutive chords
 // share their end points bit for bit.
 template <bool COUNT>
-__device__ void leaf2d(const Hot2 *__restrict__ nd, const Prim2 *__restrict__ prims, double qx, double qy,
-                       double eps_on, AngleAcc &A, Ctr &ctr, bool &overflow)
+__device__ void leaf2d(const Hot2 *__restrict__ nd, const double *bb, const Prim2 *__restrict__ prims, double qx,
+                       double qy, double eps_on, AngleAcc &A, Ctr &ctr, bool &overflow)
 {
     const int leaf = -1 - nd->right;
     const Prim2 *P = prims + leaf;
@@ -196,7 +196,7 @@ __device__ void leaf2d(const Hot2 *__restrict__ nd, const Prim2 *__restrict__ pr
         by[i] = fma(-qy, w, P->h[3 * i + 1]);
     }
     if (COUNT) ctr.v[GWN_C_LEAVES]++;
-    const bool outside = qx < nd->a[0] || qy < nd->a[1] || qx > nd->a[2] || qy > nd->a[3];
+    const bool outside = qx < bb[0] || qy < bb[1] || qx > bb[2] || qy > bb[3];
     if (outside || nd->degree == 1) {
         if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
         angle_add_chord(A, bx[0] * by[3] - by[0] * bx[3], bx[0] * bx[3] + by[0] * by[3]);
@@ -292,6 +292,24 @@ __device__ __forceinline__ T taylor2d(T dx, T dy, T d2, const T *m, int order)
     return -(ur * ti + ui * tr);   // -Im(u * t)
 }
 
+// Same term at a compile-time order: fully unrolled, so the cluster's
+// moments are requested in one go instead of one load per Horner step.
+template <typename T, int ORDER>
+__device__ __forceinline__ T taylor2d_fixed(T dx, T dy, T d2, const T *__restrict__ m)
+{
+    const T inv = fast_rcp(d2);
+    const T ur = dx * inv, ui = -dy * inv;
+    T tr = m[2 * ORDER], ti = m[2 * ORDER + 1];
+#pragma unroll
+    for (int k = ORDER - 1; k >= 0; --k) {
+        const T nr = m[2 * k] + ur * tr - ui * ti;
+        const T ni = m[2 * k + 1] + ur * ti + ui * tr;
+        tr = nr;
+        ti = ni;
+    }
+    return -(ur * ti + ui * tr);
+}
+
 // Traversal of one wave over a 2D model.  `mask`: lanes taking part (wave
 // uniform).  F32: far-field tests and Taylor terms in FP32 (mixed form).
 template <bool F32, bool COUNT>
@@ -316,9 +334,12 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     while (true) {
         const Hot2 *hd = hot + cur;
         const int right = hd->right;
+        // the record's four doubles are used on both paths below, so they
+        // are requested together with `right`
+        const double bb[4] = {hd->a[0], hd->a[1], hd->a[2], hd->a[3]};
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            if (active) leaf2d<COUNT>(hd, prims, qx, qy, M.eps_on, A, ctr, overflow);
+            if (active) leaf2d<COUNT>(hd, bb, prims, qx, qy, M.eps_on, A, ctr, overflow);
         } else {
             bool far = false;
             if (active) {
@@ -328,12 +349,16 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                     const float d2 = dx * dx + dy * dy;
                     far = d2 > beta2f * hd->fr2;
                     if (far)
-                        acc += (double)taylor2d<float>(dx, dy, d2, nodes[cur].fm, min(M.order, kMaxOrder2D - 1));
+                        acc += M.order >= kMaxOrder2D - 1
+                                   ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, nodes[cur].fm)
+                                   : (double)taylor2d<float>(dx, dy, d2, nodes[cur].fm, M.order);
                 } else {
-                    const double dx = qx - hd->a[0], dy = qy - hd->a[1];
+                    const double dx = qx - bb[0], dy = qy - bb[1];
                     const double d2 = dx * dx + dy * dy;
-                    far = d2 > beta2 * hd->a[2];
-                    if (far) acc += taylor2d<double>(dx, dy, d2, nodes[cur].m, M.order);
+                    far = d2 > beta2 * bb[2];
+                    if (far)
+                        acc += M.order == kMaxOrder2D ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, nodes[cur].m)
+                                                      : taylor2d<double>(dx, dy, d2, nodes[cur].m, M.order);
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }

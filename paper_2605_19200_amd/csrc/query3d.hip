@@ -139,6 +139,48 @@ __device__ __forceinline__ T multipole3d(T sx, T sy, T sz, const T *__restrict__
 
 // Traversal of one wave over a 3D model; returns the lane's solid angle of
 // the far field and the node-set leaves, and records its near leaves.
+// Same sum at a compile-time degree: fully unrolled, so the cluster's moments
+// are requested in a few wide loads instead of one load per term.
+template <typename T, int L>
+__device__ __forceinline__ T multipole3d_fixed(T sx, T sy, T sz, const T *__restrict__ mp)
+{
+    const T ir = mp[0];
+    const T x = sx * ir, y = sy * ir, z = sz * ir;
+    const T inv2 = T(1) / (x * x + y * y + z * z);
+    T mmr = sqrt(inv2), mmi = T(0);
+    T omega = T(0);
+#pragma unroll
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) {
+            const T f = T(2 * m - 1) * inv2;
+            const T nr = (mmr * x - mmi * y) * f;
+            const T ni = (mmr * y + mmi * x) * f;
+            mmr = nr;
+            mmi = ni;
+        }
+        const T wgt = m == 0 ? T(1) : T(2);
+        T pr = T(0), pi = T(0), cr = mmr, ci = mmi;
+#pragma unroll
+        for (int l = m; l <= L; ++l) {
+            if (l > m) {
+                const T a = T(2 * l - 1) * z * inv2;
+                const T b = T((l + m - 1) * (l - m - 1)) * inv2;
+                const T nr = a * cr - b * pr;
+                const T ni = a * ci - b * pi;
+                pr = cr;
+                pi = ci;
+                cr = nr;
+                ci = ni;
+            }
+            if (l >= 1) {
+                const int k = l * (l + 1) / 2 - 1 + m;
+                omega += wgt * (cr * mp[2 + 2 * k] - ci * mp[3 + 2 * k]);
+            }
+        }
+    }
+    return omega;
+}
+
 template <bool F32, bool COUNT>
 __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz, uint64_t mask, StackLDS &S, int w,
                              int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
@@ -167,18 +209,20 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
                     const float sx = nd->fc[0] - qxf, sy = nd->fc[1] - qyf, sz = nd->fc[2] - qzf;
                     const float r2 = sx * sx + sy * sy + sz * sz;
                     far = r2 > beta2f * nd->fr2;
-                    if (far)
-                        acc_far += (double)multipole3d<float>(-sx, -sy, -sz,
-                                                              (const float *)M.fmpole + (size_t)cur * kMpoleStride,
-                                                              M.order + 1);
+                    if (far) {
+                        const float *mp = (const float *)M.fmpole + (size_t)cur * kMpoleStride;
+                        acc_far += M.order + 1 == kMaxL3 ? (double)multipole3d_fixed<float, kMaxL3>(-sx, -sy, -sz, mp)
+                                                         : (double)multipole3d<float>(-sx, -sy, -sz, mp, M.order + 1);
+                    }
                 } else {
                     const double sx = nd->c[0] - qx, sy = nd->c[1] - qy, sz = nd->c[2] - qz;
                     const double r2 = sx * sx + sy * sy + sz * sz;
                     far = r2 > beta2 * nd->r2;
-                    if (far)
-                        acc_far += multipole3d<double>(-sx, -sy, -sz,
-                                                       (const double *)M.mpole + (size_t)cur * kMpoleStride,
-                                                       M.order + 1);
+                    if (far) {
+                        const double *mp = (const double *)M.mpole + (size_t)cur * kMpoleStride;
+                        acc_far += M.order + 1 == kMaxL3 ? multipole3d_fixed<double, kMaxL3>(-sx, -sy, -sz, mp)
+                                                         : multipole3d<double>(-sx, -sy, -sz, mp, M.order + 1);
+                    }
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }
