@@ -123,13 +123,22 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> 
         Hot2 &t = hot[i];
         std::memset(&t, 0, sizeof t);
         if (h.is_leaf) {
-            for (int k = 0; k < 4; ++k) t.a[k] = n.m[k];
+            const double *lh = &m.leaf_h[12 * (size_t)h.leaf];
+            t.a[0] = lh[0] / lh[2]; t.a[1] = lh[1] / lh[2];
+            t.a[2] = lh[9] / lh[11]; t.a[3] = lh[10] / lh[11];
+            for (int k = 0; k < 2; ++k) {
+                float lo = (float)h.lo[k], hi = (float)h.hi[k];
+                if ((double)lo > h.lo[k]) lo = std::nextafter(lo, -INFINITY);
+                if ((double)hi < h.hi[k]) hi = std::nextafter(hi, INFINITY);
+                t.f[k] = lo;
+                t.f[2 + k] = hi;
+            }
         } else {
             t.a[0] = n.c[0]; t.a[1] = n.c[1]; t.a[2] = n.r2;
+            t.f[0] = n.fc[0]; t.f[1] = n.fc[1]; t.f[2] = n.fr2;
         }
         t.right = n.right;
         t.degree = n.degree;
-        t.fc[0] = n.fc[0]; t.fc[1] = n.fc[1]; t.fr2 = n.fr2;
     }
     prims.assign(m.leaf_src.size(), Prim2{});
     for (size_t l = 0; l < prims.size(); ++l)

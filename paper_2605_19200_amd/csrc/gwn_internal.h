@@ -48,17 +48,18 @@ static_assert(sizeof(Node2) == 256, "Node2 must be two 128-byte lines");
 // 2D traversal record, 64 bytes, one array of them beside the Node2 array
 // (same DFS index).  It holds everything a node test or a leaf's fast path
 // reads, so the traversal's working set stays small enough for each XCD's
-// L2: internal nodes a = (c.x, c.y, r^2, 0) with the FP32 copies, leaves
-// a = control-point AABB (lo.x, lo.y, hi.x, hi.y); `right` and `degree` as
-// in Node2.  The moments stay in Node2 and are read for accepted clusters
-// only.
+// L2.  Internal node: a = (c.x, c.y, r^2, 0), f = the same in FP32 for the
+// mixed form's pass.  Leaf: a = the curve's end points (x0, y0, x3, y3),
+// f = its control-point AABB (lo.x, lo.y, hi.x, hi.y) rounded outward to
+// FP32, so the chord angle of a query outside the box needs no other load.
+// `right` and `degree` as in Node2.  The moments stay in Node2 and are read
+// for accepted clusters only.
 struct alignas(64) Hot2 {
     double a[4];
     int32_t right;
     int32_t degree;
-    float fc[2];
-    float fr2;
-    float pad[3];
+    float f[4];
+    float pad[2];
 };
 static_assert(sizeof(Hot2) == 64, "Hot2 must be 64 bytes");
 

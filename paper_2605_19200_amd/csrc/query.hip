@@ -183,9 +183,19 @@ __device__ __forceinline__ double lerp_exact(double a, double b, double t, doubl
 // The end point of each piece is carried to the next so consecutive chords
 // share their end points bit for bit.
 template <bool COUNT>
-__device__ void leaf2d(const Hot2 *__restrict__ nd, const double *bb, const Prim2 *__restrict__ prims, double qx,
-                       double qy, double eps_on, AngleAcc &A, Ctr &ctr, bool &overflow)
+__device__ void leaf2d(const Hot2 *__restrict__ nd, const double *ends, const float *box,
+                       const Prim2 *__restrict__ prims, double qx, double qy, double eps_on, AngleAcc &A, Ctr &ctr,
+                       bool &overflow)
 {
+    if (COUNT) ctr.v[GWN_C_LEAVES]++;
+    const bool outside = qx < (double)box[0] || qy < (double)box[1] || qx > (double)box[2] || qy > (double)box[3];
+    if (outside || nd->degree == 1) {
+        // chord from the end points held in the traversal record
+        if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
+        const double ax = ends[0] - qx, ay = ends[1] - qy, bx3 = ends[2] - qx, by3 = ends[3] - qy;
+        angle_add_chord(A, ax * by3 - ay * bx3, ax * bx3 + ay * by3);
+        return;
+    }
     const int leaf = -1 - nd->right;
     const Prim2 *P = prims + leaf;
     double bx[4], by[4];
@@ -194,13 +204,6 @@ __device__ void leaf2d(const Hot2 *__restrict__ nd, const double *bb, const Prim
         double w = P->h[3 * i + 2];
         bx[i] = fma(-qx, w, P->h[3 * i]);
         by[i] = fma(-qy, w, P->h[3 * i + 1]);
-    }
-    if (COUNT) ctr.v[GWN_C_LEAVES]++;
-    const bool outside = qx < bb[0] || qy < bb[1] || qx > bb[2] || qy > bb[3];
-    if (outside || nd->degree == 1) {
-        if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
-        angle_add_chord(A, bx[0] * by[3] - by[0] * bx[3], bx[0] * bx[3] + by[0] * by[3]);
-        return;
     }
     if (!(fabs(qx) < INFINITY && fabs(qy) < INFINITY)) { A.extra = NAN; return; }
     // On-boundary rule: a piece whose control points all lie within eps_on
@@ -334,20 +337,21 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     while (true) {
         const Hot2 *hd = hot + cur;
         const int right = hd->right;
-        // the record's four doubles are used on both paths below, so they
-        // are requested together with `right`
+        // the record's fields are used on both paths below, so they are
+        // requested together with `right`
         const double bb[4] = {hd->a[0], hd->a[1], hd->a[2], hd->a[3]};
+        const float ff[4] = {hd->f[0], hd->f[1], hd->f[2], hd->f[3]};
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            if (active) leaf2d<COUNT>(hd, bb, prims, qx, qy, M.eps_on, A, ctr, overflow);
+            if (active) leaf2d<COUNT>(hd, bb, ff, prims, qx, qy, M.eps_on, A, ctr, overflow);
         } else {
             bool far = false;
             if (active) {
                 if (COUNT) ctr.v[GWN_C_NODES]++;
                 if (F32) {
-                    const float dx = qxf - hd->fc[0], dy = qyf - hd->fc[1];
+                    const float dx = qxf - ff[0], dy = qyf - ff[1];
                     const float d2 = dx * dx + dy * dy;
-                    far = d2 > beta2f * hd->fr2;
+                    far = d2 > beta2f * ff[2];
                     if (far)
                         acc += M.order >= kMaxOrder2D - 1
                                    ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, nodes[cur].fm)
