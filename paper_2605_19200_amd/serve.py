@@ -12,9 +12,10 @@ A request is (model, host query points).  The scheduling loop
   ``max_launch`` queries -- whose device bytes (points, outputs and the
   library's per-query scratch) fit in what is left of the byte budget;
 * issues, on the slot's stream: a pinned host -> device copy of the points,
-  one ``gwn_query_batch`` over the pieces (one segment per piece, each piece
-  of a request contiguous in the output), and the device -> host copies of
-  the values and containment flags; then records an event;
+  one ``gwn_query_batch`` over the pieces (the pieces of each model side by
+  side as one segment, so the sort interleaves their queries; each piece
+  contiguous in the output), and the device -> host copies of the values
+  and containment flags; then records an event;
 * polls the events, hands the values back to their requests and releases
   their bytes.  A request is complete when its last piece is.
 
@@ -210,20 +211,30 @@ class Server:
             nbytes += b
         if not take:
             return False
-        # gather points into the slot's pinned buffer
+        # gather points into the slot's pinned buffer, the pieces of each
+        # model next to each other: one segment per model, so the library's
+        # space-filling-curve sort interleaves the queries of all requests
+        # for that model (denser waves; values do not depend on wave mates)
+        take.sort(key=lambda p: p.req.model)
         h_pts = self._pinned(s, "pts", nq * dim, torch.float64)
         hp = h_pts.numpy().reshape(nq, dim)
         offsets = [0]
+        seg_models, seg_off = [], [0]
         for p in take:
             c = p.end - p.begin
             hp[offsets[-1]:offsets[-1] + c] = p.req.points[p.begin:p.end]
             offsets.append(offsets[-1] + c)
+            if seg_models and seg_models[-1] == p.req.model:
+                seg_off[-1] = offsets[-1]
+            else:
+                seg_models.append(p.req.model)
+                seg_off.append(offsets[-1])
         with torch.cuda.stream(s.stream):
             d_pts = torch.empty(nq * dim, dtype=torch.float64, device=self.device)
             d_w = torch.empty(nq, dtype=torch.float64, device=self.device)
             d_in = torch.empty(nq, dtype=torch.uint8, device=self.device)
             d_pts.copy_(h_pts, non_blocking=True)
-            G.gwn_query_batch([self.models[p.req.model].h for p in take], np.asarray(offsets, np.int64), d_pts, d_w,
+            G.gwn_query_batch([self.models[m].h for m in seg_models], np.asarray(seg_off, np.int64), d_pts, d_w,
                               d_in, s.stream)
             h_w = self._pinned(s, "w", nq, torch.float64)
             h_in = self._pinned(s, "in", nq, torch.uint8)
