@@ -22,12 +22,12 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // -1 - leaf_index there.
 // ---------------------------------------------------------------------------
 
-// 2D node, two 128-byte lines.  Internal: centroid, squared AABB half
-// diagonal and the complex form of the centred moments m_0..m_8 with
+// 2D node, three 128-byte lines.  Internal: centroid, squared AABB half
+// diagonal and the complex form of the centred moments m_0..m_12 with
 // m_k = integral (z - c)^k dz over the cluster's chords (re, im pairs).
 // Leaf: m[0..3] holds the leaf's control-point AABB (lo.x, lo.y, hi.x,
-// hi.y).  The float fields mirror c, r2 and m_0..m_7 for the FP32 pass.
-constexpr int kMaxOrder2D = 8;
+// hi.y).  The float fields mirror c, r2 and m_0..m_11 for the FP32 pass.
+constexpr int kMaxOrder2D = 12;
 constexpr int kMaxOrder3D = 6;   // harmonic degree <= 7, see multipole3d.h
 constexpr int kMaxL3 = kMaxOrder3D + 1;   // highest solid-harmonic degree
 constexpr int kMpoleTerms = 35;           // (l, m) with 1 <= l <= 7, 0 <= m <= l
@@ -43,7 +43,7 @@ struct alignas(128) Node2 {
     float fm[2 * kMaxOrder2D];
     float pad[1];
 };
-static_assert(sizeof(Node2) == 256, "Node2 must be two 128-byte lines");
+static_assert(sizeof(Node2) == 384, "Node2 must be three 128-byte lines");
 
 // 2D traversal record, 64 bytes, one array of them beside the Node2 array
 // (same DFS index).  It holds everything a node test or a leaf's fast path

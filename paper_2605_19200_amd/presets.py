@@ -1,23 +1,24 @@
-"""Production parameter sets of the engine's query forms (2D).
+"""Production parameter sets of the engine's query forms.
 
-FP64 form: the smallest far-field factor beta (and its expansion order) whose
-maximum |w - w_direct| over the checked query sets (all of the star loop's
-4096 queries; 3328 queries of the SVG-like drawing) stays below 2.5e-7, a 4x
-margin on the 1e-6 target.  Measured sweep (beta at which the bound is met,
-1024^2 grid throughput on one MI355X):
-    order 2: beta 64 (11.3 M q/s)    order 4: beta 16 (30 M q/s)
-    order 6: beta 8  (75 M q/s)      order 8: beta 5  (135 M q/s)
-FP64_2D uses order 8 at beta 5; PAPER_ORDER_2D keeps the paper's default
-order 2 with the beta that meets the same bound.
-Mixed form: FP32 far-field pass at beta_mixed = 2 (order 7, the highest
-order the FP32 node mirror holds), then the FP64 form on every query with
-|w - 0.5| < 1e-2.
+FP64 form (2D): the smallest far-field factor beta (and its expansion order)
+whose maximum |w - w_direct| over the checked query sets (all of the star
+loop's 4096 queries; 3328 queries of the SVG-like drawing) stays below
+2.5e-7, a 4x margin on the 1e-6 target.  Measured sweep (beta at which the
+bound is met, 1024^2 grid throughput on one MI355X):
+    order 2:  beta 64 (17 M q/s)     order 8:  beta 5 (183 M q/s)
+    order 10: beta 3.5 (237 M q/s)   order 12: beta 3 (325 M q/s)
+FP64_2D uses order 12 at beta 3 (max |dw| 1.4e-7 on the checked sets);
+PAPER_ORDER_2D keeps the paper's default order 2 with the beta that meets
+the same bound.
+Mixed form (2D): FP32 far-field pass at beta_mixed = 2 (order 11, the
+highest order the FP32 node mirror holds), then the FP64 form on every
+query with |w - 0.5| < 1e-2.
 """
 from . import gwn as G
 
-FP64_2D = dict(beta=5.0, taylor_order=8, precision=G.GWN_FP64)
+FP64_2D = dict(beta=3.0, taylor_order=12, precision=G.GWN_FP64)
 PAPER_ORDER_2D = dict(beta=64.0, taylor_order=2, precision=G.GWN_FP64)
-MIXED_2D = dict(beta=5.0, beta_mixed=2.0, taylor_order=8, precision=G.GWN_MIXED, reclass_band=1e-2)
+MIXED_2D = dict(beta=3.0, beta_mixed=2.0, taylor_order=12, precision=G.GWN_MIXED, reclass_band=1e-2)
 
 
 # 3D: the order-2 expansion of the paper needs beta = 16 for the same bound

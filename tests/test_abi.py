@@ -78,7 +78,7 @@ def test_set_params_validation():
     curves, _ = W.config1()
     h = G.gwn_build2d(curves, host_params())
     p = G.gwn_get_params(h)
-    p.taylor_order = 9
+    p.taylor_order = 13
     with pytest.raises(G.GwnError):
         G.gwn_set_params(h, p)
     p.taylor_order = 1
