@@ -6,7 +6,7 @@ loop's 4096 queries; 3328 queries of the SVG-like drawing) stays below
 2.5e-7, a 4x margin on the 1e-6 target.  Measured sweep (beta at which the
 bound is met, 1024^2 grid throughput on one MI355X):
     order 2:  beta 64 (17 M q/s)     order 8:  beta 5 (183 M q/s)
-    order 10: beta 3.5 (237 M q/s)   order 12: beta 3 (325 M q/s)
+    order 10: beta 3.5 (237 M q/s)   order 12: beta 3 (331 M q/s)
 FP64_2D uses order 12 at beta 3 (max |dw| 1.4e-7 on the checked sets);
 PAPER_ORDER_2D keeps the paper's default order 2 with the beta that meets
 the same bound.
