@@ -111,8 +111,16 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> 
             n.right = -1 - h.leaf;
             n.degree = m.leaf_degree[h.leaf];
         } else {
-            // centred complex moments m_k = integral (z - c)^k dz (build2d)
-            std::memcpy(n.m, &m.cmom2[i * 2 * (kMaxOrder2D + 1)], sizeof(n.m));
+            // centred complex moments m_k = integral (z - c)^k dz (build2d),
+            // stored as m_k / r^(k+1); r = 0 only for a cluster of points,
+            // whose moments are all zero
+            const double *cm = &m.cmom2[i * 2 * (kMaxOrder2D + 1)];
+            for (int k = 0; k <= kMaxOrder2D; ++k) {
+                double re = cm[2 * k], im = cm[2 * k + 1];
+                for (int j = 0; j <= k && h.r > 0.0; ++j) { re /= h.r; im /= h.r; }
+                n.m[2 * k] = h.r > 0.0 ? re : 0.0;
+                n.m[2 * k + 1] = h.r > 0.0 ? im : 0.0;
+            }
             n.right = h.right;
             n.degree = 0;
         }
@@ -134,8 +142,8 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> 
                 t.f[2 + k] = hi;
             }
         } else {
-            t.a[0] = n.c[0]; t.a[1] = n.c[1]; t.a[2] = n.r2;
-            t.f[0] = n.fc[0]; t.f[1] = n.fc[1]; t.f[2] = n.fr2;
+            t.a[0] = n.c[0]; t.a[1] = n.c[1]; t.a[2] = n.r2; t.a[3] = h.r;
+            t.f[0] = n.fc[0]; t.f[1] = n.fc[1]; t.f[2] = n.fr2; t.f[3] = (float)h.r;
         }
         t.right = n.right;
         t.degree = n.degree;

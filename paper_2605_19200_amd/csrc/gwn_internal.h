@@ -23,10 +23,13 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // ---------------------------------------------------------------------------
 
 // 2D node, three 128-byte lines.  Internal: centroid, squared AABB half
-// diagonal and the complex form of the centred moments m_0..m_12 with
-// m_k = integral (z - c)^k dz over the cluster's chords (re, im pairs).
+// diagonal r^2 and the complex form of the centred moments, stored scaled
+// as m_k / r^(k+1) with m_k = integral (z - c)^k dz over the cluster's
+// chords (re, im pairs, k = 0..12), so the far field is a series in
+// r / (q - c), whose modulus is below 1 / beta for an accepted cluster.
 // Leaf: m[0..3] holds the leaf's control-point AABB (lo.x, lo.y, hi.x,
-// hi.y).  The float fields mirror c, r2 and m_0..m_11 for the FP32 pass.
+// hi.y).  The float fields mirror c, r2 and the scaled m_0..m_11 for the
+// FP32 pass.
 constexpr int kMaxOrder2D = 12;
 constexpr int kMaxOrder3D = 6;   // harmonic degree <= 7, see multipole3d.h
 constexpr int kMaxL3 = kMaxOrder3D + 1;   // highest solid-harmonic degree
@@ -48,7 +51,7 @@ static_assert(sizeof(Node2) == 384, "Node2 must be three 128-byte lines");
 // 2D traversal record, 64 bytes, one array of them beside the Node2 array
 // (same DFS index).  It holds everything a node test or a leaf's fast path
 // reads, so the traversal's working set stays small enough for each XCD's
-// L2.  Internal node: a = (c.x, c.y, r^2, 0), f = the same in FP32 for the
+// L2.  Internal node: a = (c.x, c.y, r^2, r), f = the same in FP32 for the
 // mixed form's pass.  Leaf: a = the curve's end points (x0, y0, x3, y3),
 // f = its control-point AABB (lo.x, lo.y, hi.x, hi.y) rounded outward to
 // FP32, so the chord angle of a query outside the box needs no other load.

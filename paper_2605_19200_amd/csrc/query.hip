@@ -182,13 +182,17 @@ __device__ __forceinline__ double lerp_exact(double a, double b, double t, doubl
 // its two one-sided limits (the direct value).
 // The end point of each piece is carried to the next so consecutive chords
 // share their end points bit for bit.
+// The box test runs in FP32 on q rounded to nearest: rounding is monotone
+// and the box edges are floats rounded outward, so qf < lo_f implies q < lo
+// (likewise above); a query that rounds onto an edge only takes the
+// bisection path.
 template <bool COUNT>
 __device__ void leaf2d(const Hot2 *__restrict__ nd, const double *ends, const float *box,
-                       const Prim2 *__restrict__ prims, double qx, double qy, double eps_on, AngleAcc &A, Ctr &ctr,
-                       bool &overflow)
+                       const Prim2 *__restrict__ prims, double qx, double qy, float qxf, float qyf, double eps_on,
+                       AngleAcc &A, Ctr &ctr, bool &overflow)
 {
     if (COUNT) ctr.v[GWN_C_LEAVES]++;
-    const bool outside = qx < (double)box[0] || qy < (double)box[1] || qx > (double)box[2] || qy > (double)box[3];
+    const bool outside = qxf < box[0] || qyf < box[1] || qxf > box[2] || qyf > box[3];
     if (outside || nd->degree == 1) {
         // chord from the end points held in the traversal record
         if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES]++; }
@@ -279,38 +283,60 @@ __device__ void leaf2d(const Hot2 *__restrict__ nd, const double *ends, const fl
 // Far-field contribution of an accepted 2D cluster, as an angle in radians.
 // The order-p Taylor expansion of Eq. taylor about the centroid c equals
 // -Im( sum_{k<=p} m_k u^{k+1} ) with u = 1/(q - c) and m_k = int (z - c)^k dz
-// (complex form of the centred moments; Horner in u).
+// (complex form of the centred moments).  With the moments stored as
+// m_k / r^(k+1) the series runs in v = r u, |v| < 1 / beta, whose powers
+// stay in range at any model scale; each moment then enters as a
+// multiplicand (two FMAs per order) instead of as the addend of a Horner
+// step, which on gfx950 would cost two extra moves per moment.
 template <typename T>
-__device__ __forceinline__ T taylor2d(T dx, T dy, T d2, const T *m, int order)
+__device__ __forceinline__ T taylor2d(T dx, T dy, T d2, T r, const T *m, int order)
 {
-    const T inv = fast_rcp(d2);   // d2 > beta^2 r^2 > 0 for an accepted cluster
-    const T ur = dx * inv, ui = -dy * inv;
-    T tr = m[2 * order], ti = m[2 * order + 1];
-    for (int k = order - 1; k >= 0; --k) {
-        const T nr = m[2 * k] + ur * tr - ui * ti;
-        const T ni = m[2 * k + 1] + ur * ti + ui * tr;
-        tr = nr;
-        ti = ni;
+    const T s = r * fast_rcp(d2);   // d2 > beta^2 r^2 > 0 for an accepted cluster
+    const T vr = dx * s, vi = -dy * s;
+    T pr = vr, pi = vi;
+    T a0 = m[0] * pi, a1 = m[1] * pr;   // two chains: Re(m) Im(v^j), Im(m) Re(v^j)
+    for (int k = 1; k <= order; ++k) {
+        const T nr = pr * vr - pi * vi;
+        const T ni = pr * vi + pi * vr;
+        pr = nr;
+        pi = ni;
+        a0 = fma(m[2 * k], pi, a0);
+        a1 = fma(m[2 * k + 1], pr, a1);
     }
-    return -(ur * ti + ui * tr);   // -Im(u * t)
+    return -(a0 + a1);   // -Im(sum m_k v^(k+1))
 }
 
 // Same term at a compile-time order: fully unrolled, so the cluster's
-// moments are requested in one go instead of one load per Horner step.
+// moments are requested in one go instead of one load per step.  The FP32
+// instance keeps Horner's rule in v (measured faster for 32-bit operands).
 template <typename T, int ORDER>
-__device__ __forceinline__ T taylor2d_fixed(T dx, T dy, T d2, const T *__restrict__ m)
+__device__ __forceinline__ T taylor2d_fixed(T dx, T dy, T d2, T r, const T *__restrict__ m)
 {
-    const T inv = fast_rcp(d2);
-    const T ur = dx * inv, ui = -dy * inv;
-    T tr = m[2 * ORDER], ti = m[2 * ORDER + 1];
+    const T s = r * fast_rcp(d2);
+    const T vr = dx * s, vi = -dy * s;
+    if constexpr (sizeof(T) == 4) {
+        T tr = m[2 * ORDER], ti = m[2 * ORDER + 1];
 #pragma unroll
-    for (int k = ORDER - 1; k >= 0; --k) {
-        const T nr = m[2 * k] + ur * tr - ui * ti;
-        const T ni = m[2 * k + 1] + ur * ti + ui * tr;
-        tr = nr;
-        ti = ni;
+        for (int k = ORDER - 1; k >= 0; --k) {
+            const T nr = m[2 * k] + vr * tr - vi * ti;
+            const T ni = m[2 * k + 1] + vr * ti + vi * tr;
+            tr = nr;
+            ti = ni;
+        }
+        return -(vr * ti + vi * tr);   // -Im(v t)
     }
-    return -(ur * ti + ui * tr);
+    T pr = vr, pi = vi;
+    T a0 = m[0] * pi, a1 = m[1] * pr;
+#pragma unroll
+    for (int k = 1; k <= ORDER; ++k) {
+        const T nr = pr * vr - pi * vi;
+        const T ni = pr * vi + pi * vr;
+        pr = nr;
+        pi = ni;
+        a0 = fma(m[2 * k], pi, a0);
+        a1 = fma(m[2 * k + 1], pr, a1);
+    }
+    return -(a0 + a1);
 }
 
 // Traversal of one wave over a 2D model.  `mask`: lanes taking part (wave
@@ -343,7 +369,7 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
         const float ff[4] = {hd->f[0], hd->f[1], hd->f[2], hd->f[3]};
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            if (active) leaf2d<COUNT>(hd, bb, ff, prims, qx, qy, M.eps_on, A, ctr, overflow);
+            if (active) leaf2d<COUNT>(hd, bb, ff, prims, qx, qy, qxf, qyf, M.eps_on, A, ctr, overflow);
         } else {
             bool far = false;
             if (active) {
@@ -354,15 +380,16 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                     far = d2 > beta2f * ff[2];
                     if (far)
                         acc += M.order >= kMaxOrder2D - 1
-                                   ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, nodes[cur].fm)
-                                   : (double)taylor2d<float>(dx, dy, d2, nodes[cur].fm, M.order);
+                                   ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, ff[3], nodes[cur].fm)
+                                   : (double)taylor2d<float>(dx, dy, d2, ff[3], nodes[cur].fm, M.order);
                 } else {
                     const double dx = qx - bb[0], dy = qy - bb[1];
                     const double d2 = dx * dx + dy * dy;
                     far = d2 > beta2 * bb[2];
                     if (far)
-                        acc += M.order == kMaxOrder2D ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, nodes[cur].m)
-                                                      : taylor2d<double>(dx, dy, d2, nodes[cur].m, M.order);
+                        acc += M.order == kMaxOrder2D
+                                   ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, bb[3], nodes[cur].m)
+                                   : taylor2d<double>(dx, dy, d2, bb[3], nodes[cur].m, M.order);
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }

@@ -142,6 +142,25 @@ def test_config2_mixed_form(cfg2):
     assert np.abs(w[band] - ref[band]).max(initial=0) <= TOL   # reclassified in FP64
 
 
+@pytest.mark.parametrize("scale", [1e-9, 1e9])
+@pytest.mark.parametrize("preset", ["FP64_2D", "MIXED_2D"])
+def test_scale_invariance(cfg1, preset, scale):
+    """w is invariant under scaling of the whole scene; the far field must
+    stay in range at any model scale in both precisions (the FP32 pass
+    included), so the scaled model meets the same bars as the unit one."""
+    curves, q, ref = cfg1
+    sc = W.Curves2D(curves.degree, curves.cp_offset, curves.cp_xy * scale, curves.cp_w)
+    m = G.Model(sc, presets.params(getattr(presets, preset)))
+    w, ins = run(m, q * scale)
+    if preset == "FP64_2D":
+        check(w, ins, ref)
+    else:
+        assert np.all(np.isfinite(w))
+        assert np.abs(w - ref).max() < 5e-3
+        sure = np.abs(ref - 0.5) > BAND
+        assert np.array_equal(ins[sure].astype(bool), (ref >= 0.5)[sure])
+
+
 def test_batch_bitwise_equals_solo(cfg1, cfg2):
     c1, q1, _ = cfg1
     c2, q2, _ = cfg2
