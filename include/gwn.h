@@ -15,7 +15,8 @@
  * moments of Sec. 3.1, Karras BVH, moment up-sweep and centering) and upload
  * the result to one GPU.  gwn_query runs the query phase of Alg. 1 on the
  * GPU: BVH traversal, the far-field test ||q - centroid|| > beta * radius,
- * the order-0..2 Taylor approximation of Eq. taylor for far clusters, and
+ * the Taylor approximation of Eq. taylor (order 0..12 in 2D, 0..6 in 3D)
+ * for far clusters, and
  * direct evaluation (Sec. 3.3) of every leaf reached.
  *
  * Conventions common to every entry point:
@@ -67,6 +68,23 @@ typedef struct {
     const double *cp_xy;       /* [2 * n_cp] Euclidean points */
     const double *cp_w;        /* [n_cp] weights              */
 } gwn_curves2d;
+
+/* 2D NURBS input, converted to gwn_curves2d by gwn_nurbs2d_extract.  Curve i
+ * has degree p = degree[i] (1..3), control points cp_xy / weights cp_w at
+ * k in [cp_offset[i], cp_offset[i+1]) (n_i >= p + 1 of them; weights finite
+ * and > 0) and the knot vector knots[knot_offset[i] .. knot_offset[i+1]-1]
+ * of n_i + p + 1 finite, non-decreasing values, clamped (its first p + 1 and
+ * last p + 1 values equal) and with no interior value repeated more than
+ * p + 1 times. */
+typedef struct {
+    int64_t n_curves;
+    const int32_t *degree;       /* [n_curves]                  */
+    const int64_t *cp_offset;    /* [n_curves + 1], cp_offset[0] == 0 */
+    const double *cp_xy;         /* [2 * n_cp] Euclidean points */
+    const double *cp_w;          /* [n_cp] weights              */
+    const int64_t *knot_offset;  /* [n_curves + 1], knot_offset[0] == 0 */
+    const double *knots;         /* [n_knots]                   */
+} gwn_nurbs2d;
 
 /* 3D input: rational bicubic Bezier patches with optional trimming (Sec. 3.1,
  * Fig. quadrature_demo).  Patch i has control points
@@ -137,6 +155,25 @@ void gwn_default_params(gwn_params *p);
  * non-finite data, beta < 2), GWN_ENOMEM, GWN_EHIP, GWN_EOVERFLOW (tree deeper
  * than the traversal stack). */
 gwn_status gwn_build2d(const gwn_curves2d *curves, const gwn_params *params, gwn_handle *out);
+
+/* Bezier extraction of 2D NURBS curves (Sec. 3.2: NURBS input is split into
+ * its rational Bezier segments ahead of the adaptive subdivision).  Each knot
+ * span [t_k, t_k+1) of positive length gives one segment of the curve's
+ * degree, whose control points are the blossom values of the span at
+ * (t_k^(p-j), t_k+1^j), j = 0..p, in homogeneous coordinates; zero-length
+ * spans give none.  Segments keep the curve order and the parameter
+ * direction, so the output describes the same point set with the same
+ * orientation and can be passed to gwn_build2d as it is.
+ * Two calls: with degree == NULL only *n_segments and *n_points are written
+ * (the output sizes).  Then, with *n_segments and *n_points holding the
+ * capacities of degree[], cp_offset[] (capacity + 1 entries), cp_xy[]
+ * (2 * capacity) and cp_w[], the arrays are filled and the two counts
+ * receive the sizes written.  All arrays are host memory owned by the
+ * caller.  Errors: GWN_EINVAL (NULL pointers, bad degree, offsets, knot
+ * count or order, unclamped knots, non-finite data, weight <= 0, capacity
+ * too small). */
+gwn_status gwn_nurbs2d_extract(const gwn_nurbs2d *in, int64_t *n_segments, int64_t *n_points,
+                               int32_t *degree, int64_t *cp_offset, double *cp_xy, double *cp_w);
 
 /* Build a 3D model (Alg. 1 preprocessing, moments by Gauss-Legendre quadrature
  * over the trimmed domain via Green's theorem, Sec. 3.1).  Errors as for

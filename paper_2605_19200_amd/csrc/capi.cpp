@@ -306,6 +306,38 @@ extern "C" gwn_status gwn_build2d(const gwn_curves2d *curves, const gwn_params *
     });
 }
 
+extern "C" gwn_status gwn_nurbs2d_extract(const gwn_nurbs2d *in, int64_t *n_segments, int64_t *n_points,
+                                          int32_t *degree, int64_t *cp_offset, double *cp_xy, double *cp_w)
+{
+    if (!in || !n_segments || !n_points) return fail(GWN_EINVAL, "NULL input or count pointer");
+    std::vector<int32_t> deg;
+    std::vector<int64_t> off;
+    std::vector<double> xy, w;
+    std::string err;
+    try {
+        if (!extract_nurbs2d(*in, deg, off, xy, w, err)) return fail(GWN_EINVAL, err);
+    } catch (const std::bad_alloc &) {
+        return fail(GWN_ENOMEM, "host allocation failed during NURBS extraction");
+    }
+    const int64_t ns = (int64_t)deg.size(), np = (int64_t)w.size();
+    if (!degree) {
+        *n_segments = ns;
+        *n_points = np;
+        return GWN_OK;
+    }
+    if (!cp_offset || !cp_xy || !cp_w) return fail(GWN_EINVAL, "NULL output array");
+    if (*n_segments < ns || *n_points < np)
+        return fail(GWN_EINVAL, "output capacity too small: need " + std::to_string(ns) + " segments and " +
+                                    std::to_string(np) + " points");
+    std::copy(deg.begin(), deg.end(), degree);
+    std::copy(off.begin(), off.end(), cp_offset);
+    std::copy(xy.begin(), xy.end(), cp_xy);
+    std::copy(w.begin(), w.end(), cp_w);
+    *n_segments = ns;
+    *n_points = np;
+    return GWN_OK;
+}
+
 extern "C" gwn_status gwn_build3d(const gwn_patches3d *patches, const gwn_params *params, gwn_handle *out)
 {
     if (!patches) return fail(GWN_EINVAL, "patches is NULL");

@@ -225,6 +225,10 @@ struct Model {
 // builders (host)
 gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, std::string &err);
 gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, std::string &err);
+// Bezier extraction of 2D NURBS curves (nurbs.cpp); false with err set on
+// invalid input
+bool extract_nurbs2d(const gwn_nurbs2d &in, std::vector<int32_t> &deg, std::vector<int64_t> &off,
+                     std::vector<double> &xy, std::vector<double> &w, std::string &err);
 // upload to device and fill m.dev
 gwn_status upload_model(Model &m, std::string &err);
 void refresh_dev_params(Model &m);

@@ -22,7 +22,8 @@ COUNTER_NAMES = ["nodes", "far", "leaves", "leaf_fast", "pieces", "angles", "rec
 GWN_NCOUNTERS = len(COUNTER_NAMES)
 GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX, GWN_I_MULTIPOLE = range(7)
 
-EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_set_params", "gwn_get_params", "gwn_query",
+EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
+            "gwn_get_params", "gwn_query",
             "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
             "gwn_free", "gwn_last_error"]
 
@@ -43,6 +44,12 @@ class gwn_params(ctypes.Structure):
 class gwn_curves2d(ctypes.Structure):
     _fields_ = [("n_curves", ctypes.c_int64), ("degree", ctypes.c_void_p), ("cp_offset", ctypes.c_void_p),
                 ("cp_xy", ctypes.c_void_p), ("cp_w", ctypes.c_void_p)]
+
+
+class gwn_nurbs2d(ctypes.Structure):
+    _fields_ = [("n_curves", ctypes.c_int64), ("degree", ctypes.c_void_p), ("cp_offset", ctypes.c_void_p),
+                ("cp_xy", ctypes.c_void_p), ("cp_w", ctypes.c_void_p), ("knot_offset", ctypes.c_void_p),
+                ("knots", ctypes.c_void_p)]
 
 
 class gwn_patches3d(ctypes.Structure):
@@ -67,6 +74,8 @@ def lib():
         for name, args in [
             ("gwn_build2d", [ctypes.POINTER(gwn_curves2d), ctypes.POINTER(gwn_params), ctypes.POINTER(vp)]),
             ("gwn_build3d", [ctypes.POINTER(gwn_patches3d), ctypes.POINTER(gwn_params), ctypes.POINTER(vp)]),
+            ("gwn_nurbs2d_extract", [ctypes.POINTER(gwn_nurbs2d), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     vp, vp, vp, vp]),
             ("gwn_set_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_get_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_query", [vp, vp, i64, vp, vp, vp]),
@@ -126,6 +135,26 @@ def gwn_build3d(patches, params: gwn_params | None = None):
     h = ctypes.c_void_p()
     _check(lib().gwn_build3d(ctypes.byref(c), ctypes.byref(params) if params else None, ctypes.byref(h)))
     return h
+
+
+def gwn_nurbs2d_extract(nurbs):
+    """Bezier segments of a ``workloads.Nurbs2D`` as a ``workloads.Curves2D``
+    (two calls of the C entry point: sizes, then the arrays)."""
+    from .workloads import Curves2D
+    arrs = [_np(nurbs.degree, np.int32), _np(nurbs.cp_offset, np.int64), _np(nurbs.cp_xy, np.float64),
+            _np(nurbs.cp_w, np.float64), _np(nurbs.knot_offset, np.int64), _np(nurbs.knots, np.float64)]
+    c = gwn_nurbs2d(nurbs.n, *[_p(a) for a in arrs])
+    ns, npt = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().gwn_nurbs2d_extract(ctypes.byref(c), ctypes.byref(ns), ctypes.byref(npt), None, None, None, None))
+    if ns.value == 0:
+        return Curves2D.from_list([])
+    deg = np.zeros(ns.value, np.int32)
+    off = np.zeros(ns.value + 1, np.int64)
+    xy = np.zeros((npt.value, 2), np.float64)
+    w = np.zeros(npt.value, np.float64)
+    _check(lib().gwn_nurbs2d_extract(ctypes.byref(c), ctypes.byref(ns), ctypes.byref(npt), _p(deg), _p(off),
+                                     _p(xy), _p(w)))
+    return Curves2D(deg, off, xy, w)
 
 
 def gwn_set_params(h, params: gwn_params):

@@ -127,6 +127,38 @@ class Curves2D:
 
 
 @dataclasses.dataclass
+class Nurbs2D:
+    """2D NURBS curves (input of ``gwn.gwn_nurbs2d_extract``): degree 1..3,
+    clamped knot vectors, CSR control points and knots."""
+    degree: np.ndarray       # int32[n]
+    cp_offset: np.ndarray    # int64[n+1]
+    cp_xy: np.ndarray        # float64[n_cp, 2]
+    cp_w: np.ndarray         # float64[n_cp]
+    knot_offset: np.ndarray  # int64[n+1]
+    knots: np.ndarray        # float64[n_knots]
+
+    @property
+    def n(self) -> int:
+        return int(self.degree.shape[0])
+
+    @staticmethod
+    def from_list(curves) -> "Nurbs2D":
+        """``curves``: iterable of (degree, points[k,2], weights[k], knots[k+degree+1])."""
+        deg, off, xy, w, koff, kn = [], [0], [], [], [0], []
+        for p, pts, wt, U in curves:
+            pts = np.asarray(pts, dtype=np.float64).reshape(-1, 2)
+            deg.append(int(p))
+            off.append(off[-1] + pts.shape[0])
+            xy.append(pts)
+            w.append(np.asarray(wt, dtype=np.float64).reshape(-1))
+            kn.append(np.asarray(U, dtype=np.float64).reshape(-1))
+            koff.append(koff[-1] + kn[-1].shape[0])
+        cat = (lambda a, shape: np.ascontiguousarray(np.concatenate(a)) if a else np.zeros(shape))
+        return Nurbs2D(np.asarray(deg, np.int32), np.asarray(off, np.int64), cat(xy, (0, 2)), cat(w, (0,)),
+                       np.asarray(koff, np.int64), cat(kn, (0,)))
+
+
+@dataclasses.dataclass
 class Patches3D:
     cp_xyz: np.ndarray          # float64[n,16,3]
     cp_w: np.ndarray            # float64[n,16]

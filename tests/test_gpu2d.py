@@ -161,6 +161,36 @@ def test_scale_invariance(cfg1, preset, scale):
         assert np.array_equal(ins[sure].astype(bool), (ref >= 0.5)[sure])
 
 
+def test_nurbs_scene_end_to_end(oracle):
+    """NURBS input through Bezier extraction, build and the FP64 form: a
+    closed cubic B-spline star (C2 inside, clamped at a shared end point)
+    and a NURBS circle of radius 0.3 inside it, oriented clockwise (a hole)."""
+    rng = W.Rng(81, "nurbs-scene")
+    n = 40
+    th = np.linspace(0, 2 * np.pi, n, endpoint=False)
+    rad = 1 + 0.35 * np.cos(5 * th) * rng.uniform(n, 0.6, 1.0)
+    pts = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
+    pts = np.concatenate([pts, pts[:1]])
+    w = rng.uniform(n + 1, 0.6, 1.6)
+    w[-1] = w[0]
+    U = np.concatenate([[0.0] * 4, np.linspace(0, 1, n - 1)[1:-1], [1.0] * 4])
+    s2 = np.sqrt(0.5)
+    cpts = 0.3 * np.array([(1, 0), (1, -1), (0, -1), (-1, -1), (-1, 0), (-1, 1), (0, 1), (1, 1), (1, 0)])
+    cw = [1, s2, 1, s2, 1, s2, 1, s2, 1]
+    CU = [0, 0, 0, 0.25, 0.25, 0.5, 0.5, 0.75, 0.75, 1, 1, 1]
+    N = W.Nurbs2D.from_list([(3, pts, w, U), (2, cpts, cw, CU)])
+    B = G.gwn_nurbs2d_extract(N)
+    assert B.n == (n + 1 - 3) + 4
+    lo, hi = B.cp_xy.min(0), B.cp_xy.max(0)
+    q = np.concatenate([W.Rng(82, "q").uniform((3000, 2), 0, 1) * (hi - lo) * 1.2 + lo - 0.1 * (hi - lo),
+                        0.29 * np.stack([np.cos(th), np.sin(th)], axis=1)])
+    ref = oracle.gwn2d(B, q)
+    assert np.abs(ref[-n:]).max() < 1e-9   # inside the hole
+    m = G.Model(B, presets.params(presets.FP64_2D))
+    w_, ins = run(m, q)
+    check(w_, ins, ref)
+
+
 def test_batch_bitwise_equals_solo(cfg1, cfg2):
     c1, q1, _ = cfg1
     c2, q2, _ = cfg2

@@ -147,6 +147,23 @@ def test_config4_fp64_and_mixed(cfg4):
     assert np.array_equal(insm[sure].astype(bool), (ref >= 0.5)[sure])
 
 
+@pytest.mark.parametrize("scale", [1e-6, 1e6])
+def test_scale_invariance_3d(cfg4, scale):
+    """The trimmed assembly scaled as a whole keeps its w in both forms:
+    far field, node sets and near-field rule work in scale-free units."""
+    P, qs, ref = cfg4
+    S = W.Patches3D(P.cp_xyz * scale, P.cp_w, P.trim_offset, P.trim_degree, P.trim_cp_offset,
+                    P.trim_cp_uv, P.trim_cp_w)
+    m = G.Model(S, presets.params(presets.FP64_3D))
+    w, ins = run(m, qs * scale)
+    check(w, ins, ref)
+    mm = G.Model(S, presets.params(presets.MIXED_3D))
+    wm, insm = run(mm, qs * scale)
+    assert np.all(np.isfinite(wm)) and np.abs(wm - ref).max() < 5e-3
+    sure = np.abs(ref - 0.5) > BAND
+    assert np.array_equal(insm[sure].astype(bool), (ref >= 0.5)[sure])
+
+
 def test_batch_bitwise_3d(cfg4, sphere):
     P, qs, _ = cfg4
     m1 = G.Model(P, presets.params(presets.FP64_3D))
