@@ -95,7 +95,8 @@ def bench3d(steps: int = 1) -> dict:
             m.query(pts)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
-        out[name] = {"queries_per_s": q.shape[0] / dt, "ms": dt * 1e3, "beta": pre["beta"]}
+        out[name] = {"queries_per_s": q.shape[0] / dt, "ms": dt * 1e3, "beta": pre["beta"],
+                     "leaves": int(m.inspect(G.GWN_I_SUMMARY)[0][2]), "resident_bytes": int(m.bytes()[0])}
         m.close()
         print(f"[bench] 3D {name}: {dt * 1e3:.1f} ms per grid", file=sys.stderr, flush=True)
     return out
@@ -211,6 +212,7 @@ def main():
     t_b = time.time()
     model = G.Model(curves, presets.params(presets.FP64_2D))
     build_s = time.time() - t_b
+    n_leaves = int(model.inspect(G.GWN_I_SUMMARY)[0][2])
     pts = torch.from_numpy(q).cuda()
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     ins = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -326,7 +328,9 @@ def main():
         "config": {"workload": "2D SVG-like drawing: 200 nested/overlapping loops, "
                                f"{curves.n} rational Bezier curves (degree 2-3), {args.grid}x{args.grid} grid",
                    "queries": n, "curves": curves.n, "beta": presets.FP64_2D["beta"],
-                   "taylor_order": presets.FP64_2D["taylor_order"], "build_s": round(build_s, 3)},
+                   "taylor_order": presets.FP64_2D["taylor_order"],
+                   "max_diag_frac": presets.FP64_2D.get("max_diag_frac", 0.1), "leaves": n_leaves,
+                   "build_s": round(build_s, 3)},
         "accuracy": {"sample": len(acc_idx), "fp64_max_abs_dw": float(err64.max()),
                      "fp64_containment_mismatch_outside_1e-3": mism64,
                      "mixed_max_abs_dw": float(errm.max()), "mixed_p99_abs_dw": float(np.quantile(errm, 0.99)),

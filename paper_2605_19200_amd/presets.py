@@ -1,24 +1,32 @@
 """Production parameter sets of the engine's query forms.
 
-FP64 form (2D): the smallest far-field factor beta (and its expansion order)
-whose maximum |w - w_direct| over the checked query sets (all of the star
-loop's 4096 queries; 3328 queries of the SVG-like drawing) stays below
-2.5e-7, a 4x margin on the 1e-6 target.  Measured sweep (beta at which the
-bound is met, 1024^2 grid throughput on one MI355X):
-    order 2:  beta 64 (17 M q/s)     order 8:  beta 5 (183 M q/s)
-    order 10: beta 3.5 (237 M q/s)   order 12: beta 3 (331 M q/s)
-FP64_2D uses order 12 at beta 3 (max |dw| 1.4e-7 on the checked sets);
-PAPER_ORDER_2D keeps the paper's default order 2 with the beta that meets
-the same bound.
+FP64 form (2D): the fastest (order, beta, subdivision threshold) whose
+maximum |w - w_direct| over the checked query sets (the star loop's 4096
+queries; the SVG-like drawing's full 1024^2 grid) stays below 2.5e-7, a 4x
+margin on the 1e-6 target.  Measured on one MI355X at the paper's 10%
+subdivision threshold (beta at which the bound is met, 1024^2 grid):
+    order 2:  beta 64 (17 M q/s)     order 8:  beta 4 (212 M q/s)
+    order 12: beta 3.25 (282 M q/s)  (beta 3: 2.7e-7, 313 M q/s)
+Subdividing further (Sec. 4.1: split a curve while its box diagonal is at
+least max_diag_frac of the model's) shrinks the leaves, so fewer queries
+fall inside a leaf's box and need bisection; at order 12, beta 3.25:
+    max_diag_frac 0.1: 19000 leaves, 3.72 ms, max |dw| 8.6e-8
+                  0.025: 23029 leaves, 3.03 ms, 1.5e-7
+                  0.0125: 35687 leaves, 2.68 ms, 2.2e-7  (chosen)
+                  0.00625: 65009 leaves, 2.64 ms, 4.2e-7
+FP64_2D therefore uses order 12, beta 3.25 and max_diag_frac 0.0125;
+PAPER_ORDER_2D keeps the paper's default order 2 and 10% threshold with the
+beta that meets the same bound.
 Mixed form (2D): FP32 far-field pass at beta_mixed = 2 (order 11, the
 highest order the FP32 node mirror holds), then the FP64 form on every
 query with |w - 0.5| < 1e-2.
 """
 from . import gwn as G
 
-FP64_2D = dict(beta=3.0, taylor_order=12, precision=G.GWN_FP64)
+FP64_2D = dict(beta=3.25, taylor_order=12, max_diag_frac=0.0125, precision=G.GWN_FP64)
 PAPER_ORDER_2D = dict(beta=64.0, taylor_order=2, precision=G.GWN_FP64)
-MIXED_2D = dict(beta=3.0, beta_mixed=2.0, taylor_order=12, precision=G.GWN_MIXED, reclass_band=1e-2)
+MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125, precision=G.GWN_MIXED,
+                reclass_band=1e-2)
 
 
 # 3D: the order-2 expansion of the paper needs beta = 16 for the same bound
@@ -28,6 +36,11 @@ MIXED_2D = dict(beta=3.0, beta_mixed=2.0, taylor_order=12, precision=G.GWN_MIXED
 # bodies scene, 128 of the CAD assembly, plus the near-surface test sets):
 #   order 2, beta 16: 3.9e-7    order 4, beta 8: 2.3e-7
 #   order 5, beta 5:  3.0e-7    order 6, beta 5: 1.0e-7  (chosen)
+# Subdividing untrimmed patches further (trimmed ones stay whole) would cut
+# the near-field work, as in 2D (bodies scene, 128^3 grid: 594 ms at the
+# paper's 0.1, 410 ms at 0.0125 with 29747 leaves), but the sub-patches of a
+# strongly stretched patch then miss the 1e-6 bar (|dw| 6.8e-4 on the
+# stretched-patch near-field test set), so 3D keeps the paper's threshold.
 FP64_3D = dict(beta=5.0, taylor_order=6, precision=G.GWN_FP64)
 PAPER_ORDER_3D = dict(beta=16.0, taylor_order=2, precision=G.GWN_FP64)
 MIXED_3D = dict(beta=5.0, beta_mixed=3.0, taylor_order=6, precision=G.GWN_MIXED, reclass_band=1e-2)

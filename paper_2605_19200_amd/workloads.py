@@ -324,6 +324,25 @@ def config1(seed=1, n_query=4096):
     return curves, q
 
 
+def overlapping_polygons(k, sides=15, seed=8):
+    """``k`` closed, nearly overlapping regular polygons of ``sides`` linear
+    edges (the overlap stress case of Sec. 4.3, Fig. overlap_demo):
+    polygon j is the unit polygon rotated by a seeded angle in [0, 0.02) rad
+    and scaled by 1 + U(0, 0.01), all counter-clockwise, so the winding number
+    reaches k where all of them overlap."""
+    rng = Rng(seed, "overlap")
+    rot = rng.uniform(k, 0.0, 0.02)
+    scl = 1.0 + rng.uniform(k, 0.0, 0.01)
+    curves = []
+    for j in range(k):
+        th = rot[j] + 2 * math.pi * np.arange(sides + 1) / sides
+        pts = scl[j] * np.stack([np.cos(th), np.sin(th)], axis=1)
+        pts[-1] = pts[0]
+        for e in range(sides):
+            curves.append((pts[e:e + 2], np.ones(2)))
+    return Curves2D.from_list(curves)
+
+
 def svg_like(seed=2, n_groups=50, loops_per_group=4, curves_per_loop=100, delete_frac=0.05):
     """SVG-like drawing: groups of concentric jittered loops (nested and
     overlapping), degree 2-3 rational curves, weights U(0.5, 2), loops CCW with
