@@ -165,6 +165,25 @@ double mid_iso_length(const Patch &p, int dir)
     return len;
 }
 
+// True when one of the four boundary edges of the patch is collapsed to a
+// point (all four Euclidean control points within tol of each other), as at
+// the poles of a sphere.
+bool has_collapsed_edge(const Patch &p, double tol)
+{
+    for (int e = 0; e < 4; ++e) {
+        double pt[4][3];
+        for (int t = 0; t < 4; ++t) {
+            const int i = e == 0 ? 0 : e == 1 ? 3 : t, j = e == 2 ? 0 : e == 3 ? 3 : t;
+            for (int k = 0; k < 3; ++k) pt[t][k] = p.h[i][j][k] / p.h[i][j][3];
+        }
+        double spread = 0.0;
+        for (int t = 1; t < 4; ++t)
+            for (int k = 0; k < 3; ++k) spread = std::fmax(spread, std::fabs(pt[t][k] - pt[0][k]));
+        if (spread <= tol) return true;
+    }
+    return false;
+}
+
 }  // namespace
 
 gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, std::string &err)
@@ -272,7 +291,10 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     // AABB diagonal is not below max_diag_frac of the model diagonal, in the
     // parameter direction whose middle iso-curve has the longer control
     // polygon.  Trimmed patches are kept whole (splitting them would need
-    // their trim loops clipped to each half).
+    // their trim loops clipped to each half), and so are patches with an
+    // edge collapsed to a point: the near-field rule resolves the whole
+    // polar patch, while its sub-patches at the pole put the foot point on a
+    // degenerate corner of a tiny, strongly non-uniform domain.
     const double limit = p->max_diag_frac * m.diag;
     std::vector<Patch> leaves;
     leaves.reserve(work.size());
@@ -286,7 +308,8 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         patch_aabb(it.p, l, h);
         const double dg = std::sqrt((h[0] - l[0]) * (h[0] - l[0]) + (h[1] - l[1]) * (h[1] - l[1]) +
                                     (h[2] - l[2]) * (h[2] - l[2]));
-        if (limit > 0 && dg >= limit && it.p.trim_count == 0 && it.depth < 24) {
+        if (limit > 0 && dg >= limit && it.p.trim_count == 0 && it.depth < 24 &&
+            !has_collapsed_edge(it.p, 1e-12 * m.diag)) {
             const int dir = mid_iso_length(it.p, 0) >= mid_iso_length(it.p, 1) ? 0 : 1;
             Patch L, R;
             split(it.p, dir, L, R);
