@@ -116,7 +116,7 @@ def served_benchmark(seed: int = 5, n_requests: int = 400, loads=(0.5, 0.8, 0.95
 
     t = time.time()
     geoms = [(k, g) for k, g in W.serving_models(seed, kinds=kinds)]
-    srv = serve.Server(budget_bytes=4 << 30, n_slots=2)
+    srv = serve.Server(budget_bytes=4 << 30, n_slots=4)
     for kind, g in geoms:
         srv.add_model(g, presets.params(presets.MIXED_2D if kind == "2d" else presets.MIXED_3D))
     build_s = time.time() - t
