@@ -144,6 +144,15 @@ typedef struct {
                               near-field rule has a fixed node budget, checked
                               to ~1e-9 per leaf, so the value does not change
                               results (default 1e-10)                         */
+    int32_t leaf_far;      /* Q, 3D: 1 = a leaf reached by the traversal that
+                              passes the far test ||q - c|| > beta * r itself is
+                              evaluated by its own far-field expansion, like a
+                              cluster (the same error criterion; its direct
+                              rule costs hundreds to thousands of quadrature
+                              nodes); 0 = every reached leaf is evaluated
+                              directly, as in Alg. 1.  Default 1; 2D leaves
+                              are always direct (the chord angle is exact)   */
+    int32_t reserved;      /* set to 0                                      */
 } gwn_params;
 
 /* Fill *p with the defaults listed above. */

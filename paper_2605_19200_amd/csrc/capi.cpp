@@ -44,6 +44,8 @@ extern "C" void gwn_default_params(gwn_params *p)
     p->device = 0;
     p->near_ratio = 0.25;
     p->eps_q = 1e-10;
+    p->leaf_far = 1;
+    p->reserved = 0;
 }
 
 static gwn_status check_query_params(int dim, const gwn_params *p)
@@ -59,6 +61,7 @@ static gwn_status check_query_params(int dim, const gwn_params *p)
     if (!(p->reclass_band >= 0) || !std::isfinite(p->reclass_band)) return fail(GWN_EINVAL, "bad reclass_band");
     if (!(p->near_ratio >= 0) || !std::isfinite(p->near_ratio)) return fail(GWN_EINVAL, "bad near_ratio");
     if (!(p->eps_q > 0)) return fail(GWN_EINVAL, "eps_q must be > 0");
+    if (p->leaf_far != 0 && p->leaf_far != 1) return fail(GWN_EINVAL, "leaf_far must be 0 or 1");
     return GWN_OK;
 }
 
@@ -90,6 +93,7 @@ void refresh_dev_params(Model &m)
     }
     m.dev.eps_on = p.eps_on * m.diag;
     m.dev.near_ratio2 = p.near_ratio * p.near_ratio;
+    m.dev.leaf_far = p.leaf_far;
     m.dev.eps_q = p.eps_q;
     m.dev.gl_n = p.gl_nodes;
 }
@@ -356,6 +360,7 @@ extern "C" gwn_status gwn_set_params(gwn_handle h, const gwn_params *params)
     p.precision = params->precision;
     p.reclass_band = params->reclass_band;
     p.near_ratio = params->near_ratio;
+    p.leaf_far = params->leaf_far;
     p.eps_q = params->eps_q;
     gwn_status s = check_query_params(h->m.dim, &p);
     if (s) return s;

@@ -154,7 +154,7 @@ struct DevModel {
     double near_ratio2;     // 3D: (near_ratio)^2 factor on squared AABB diagonal
     double eps_q;           // 3D near-field tolerance
     int32_t gl_n;           // 3D GL nodes
-    int32_t pad;
+    int32_t leaf_far;       // 3D: far leaves by their own expansion (gwn_params)
 };
 
 // ---------------------------------------------------------------------------

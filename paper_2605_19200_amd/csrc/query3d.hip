@@ -181,15 +181,44 @@ __device__ __forceinline__ T multipole3d_fixed(T sx, T sy, T sz, const T *__rest
     return omega;
 }
 
+// Far test of node `cur` for one lane, adding its far-field term when the
+// test passes; true when it does.
+template <bool F32>
+__device__ __forceinline__ bool far_term3d(const DevModel &M, const Node3 *__restrict__ nd, int cur, double qx,
+                                           double qy, double qz, double &acc_far)
+{
+    if (F32) {
+        const float sx = nd->fc[0] - (float)qx, sy = nd->fc[1] - (float)qy, sz = nd->fc[2] - (float)qz;
+        const float r2 = sx * sx + sy * sy + sz * sz;
+        const bool far = r2 > (float)M.beta2_mixed * nd->fr2;
+        if (far) {
+            const float *mp = (const float *)M.fmpole + (size_t)cur * kMpoleStride;
+            acc_far += M.order + 1 == kMaxL3 ? (double)multipole3d_fixed<float, kMaxL3>(-sx, -sy, -sz, mp)
+                                             : (double)multipole3d<float>(-sx, -sy, -sz, mp, M.order + 1);
+        }
+        return far;
+    }
+    const double sx = nd->c[0] - qx, sy = nd->c[1] - qy, sz = nd->c[2] - qz;
+    const double r2 = sx * sx + sy * sy + sz * sz;
+    const bool far = r2 > M.beta2 * nd->r2;
+    if (far) {
+        const double *mp = (const double *)M.mpole + (size_t)cur * kMpoleStride;
+        acc_far += M.order + 1 == kMaxL3 ? multipole3d_fixed<double, kMaxL3>(-sx, -sy, -sz, mp)
+                                         : multipole3d<double>(-sx, -sy, -sz, mp, M.order + 1);
+    }
+    return far;
+}
+
+// Traversal of one wave (Alg. 1 query loop) over a 3D model.  With
+// leaf_far, a reached leaf that passes the far test itself takes its own
+// far-field expansion, like a cluster; the rest of the reached leaves are
+// evaluated directly (node sets, or recorded for the near-field pass).
 template <bool F32, bool COUNT>
 __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz, uint64_t mask, StackLDS &S, int w,
                              int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
     const Node3 *__restrict__ nodes = (const Node3 *)M.nodes;
     const int lane = lane_id();
-    const float qxf = (float)qx, qyf = (float)qy, qzf = (float)qz;
-    const double beta2 = F32 ? M.beta2_mixed : M.beta2;
-    const float beta2f = (float)M.beta2_mixed;
     double acc_far = 0.0, acc_leaf = 0.0;
     int cur = 0;
     uint64_t curmask = mask;
@@ -200,30 +229,17 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
         const int right = nd->right;
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            acc_leaf += leaf3d<COUNT>(M, nd, cur, qx, qy, qz, active, ncnt, mylist, ctr);
+            bool far = false;
+            if (active && M.leaf_far) {
+                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far);
+                if (COUNT && far) { ctr.v[GWN_C_FAR]++; ctr.v[GWN_C_LEAVES]++; }
+            }
+            acc_leaf += leaf3d<COUNT>(M, nd, cur, qx, qy, qz, active && !far, ncnt, mylist, ctr);
         } else {
             bool far = false;
             if (active) {
                 if (COUNT) ctr.v[GWN_C_NODES]++;
-                if (F32) {
-                    const float sx = nd->fc[0] - qxf, sy = nd->fc[1] - qyf, sz = nd->fc[2] - qzf;
-                    const float r2 = sx * sx + sy * sy + sz * sz;
-                    far = r2 > beta2f * nd->fr2;
-                    if (far) {
-                        const float *mp = (const float *)M.fmpole + (size_t)cur * kMpoleStride;
-                        acc_far += M.order + 1 == kMaxL3 ? (double)multipole3d_fixed<float, kMaxL3>(-sx, -sy, -sz, mp)
-                                                         : (double)multipole3d<float>(-sx, -sy, -sz, mp, M.order + 1);
-                    }
-                } else {
-                    const double sx = nd->c[0] - qx, sy = nd->c[1] - qy, sz = nd->c[2] - qz;
-                    const double r2 = sx * sx + sy * sy + sz * sz;
-                    far = r2 > beta2 * nd->r2;
-                    if (far) {
-                        const double *mp = (const double *)M.mpole + (size_t)cur * kMpoleStride;
-                        acc_far += M.order + 1 == kMaxL3 ? multipole3d_fixed<double, kMaxL3>(-sx, -sy, -sz, mp)
-                                                         : multipole3d<double>(-sx, -sy, -sz, mp, M.order + 1);
-                    }
-                }
+                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far);
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }
             const uint64_t farmask = __ballot(active && far);
@@ -259,7 +275,7 @@ __device__ __forceinline__ int wave_segment(const LaunchTable &T, int wave)
 // far field and node-set leaves, near leaves recorded.  RECLASS: only the
 // lanes flagged by the mixed form's first near pass, in FP64.
 template <bool COUNT, bool RECLASS>
-__global__ __launch_bounds__(kBlock) void k_trav3d(LaunchTable T, const double *__restrict__ pts,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_trav3d(LaunchTable T, const double *__restrict__ pts,
                                                    const int32_t *__restrict__ perm, NearScratch NS,
                                                    long long *counters)
 {

@@ -38,7 +38,8 @@ class gwn_params(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_double), ("beta_mixed", ctypes.c_double), ("taylor_order", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reclass_band", ctypes.c_double), ("max_diag_frac", ctypes.c_double),
                 ("eps_on", ctypes.c_double), ("gl_nodes", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("near_ratio", ctypes.c_double), ("eps_q", ctypes.c_double)]
+                ("near_ratio", ctypes.c_double), ("eps_q", ctypes.c_double), ("leaf_far", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class gwn_curves2d(ctypes.Structure):

@@ -191,6 +191,26 @@ def test_nurbs_scene_end_to_end(oracle):
     check(w_, ins, ref)
 
 
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_overlapping_polygons(oracle, k):
+    """k nearly overlapping closed 15-gons (the paper's overlap stress case):
+    the oracle's w is an integer up to rounding (watertight), counting the
+    polygons that contain q, and the FP64 form holds the 1e-6 bar at any k
+    (the order-0 expansion at beta = 2 misclassifies at k = 16)."""
+    curves = W.overlapping_polygons(k)
+    q = W.bbox_queries_uniform(W.Rng(60 + k, "overlap-q"), (-1.3, -1.3), (1.3, 1.3), 4096, 1.0)
+    ref = oracle.gwn2d(curves, q)
+    assert np.abs(ref - np.rint(ref)).max() < 1e-9
+    assert ref.max() > k - 0.5 and ref.min() > -0.5
+    m = G.Model(curves, presets.params(presets.FP64_2D))
+    w, ins = run(m, q)
+    check(w, ins, ref)
+    if k == 16:
+        m0 = G.Model(curves, presets.params(presets.FP64_2D, beta=2.0, taylor_order=0, max_diag_frac=0.1))
+        w0, _ = run(m0, q)
+        assert np.abs(w0 - ref).max() > 0.05   # the order-0 error grows with the overlap
+
+
 def test_batch_bitwise_equals_solo(cfg1, cfg2):
     c1, q1, _ = cfg1
     c2, q2, _ = cfg2
