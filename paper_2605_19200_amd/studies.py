@@ -10,6 +10,8 @@ after the paper's experiments on its own datasets:
   overlap        k nearly overlapping closed 15-gons: absolute and relative
                  error and misclassifications against k       (Sec. 4.3, Fig. overlap_demo)
 
+The order, disagreement and overlap studies use the paper's 10 % subdivision
+threshold; the subdivision study runs the FP64 preset's order and beta.
 The reference is the same engine with the far field switched off (beta =
 1e8: every leaf evaluated directly), whose agreement with the FP64 oracle is
 a GPU test of its own.  Each study prints one JSON line to stdout and its
@@ -67,7 +69,7 @@ def order_beta(grid=1024):
     rows = []
     for order in (0, 1, 2, 4, 8, 12):
         for beta in (2.0, 3.0, 4.0, 6.0, 8.0, 16.0, 32.0, 64.0):
-            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order))
+            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1))
             w, ms = _run(m, qd)
             m.close()
             err = np.abs(w - ref)
@@ -94,8 +96,8 @@ def subdivision(grid=1024):
         rows.append(dict(max_diag_frac=None if frac >= 1e9 else frac, leaves=leaves, build_s=round(build_s, 3),
                          ms=round(ms, 3), max_abs_dw=float(np.abs(w - ref).max())))
         _log(f"subdivision: {frac} -> {leaves} leaves, {ms:.2f} ms")
-    return dict(study="subdivision", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid, "
-                "FP64 form (order 12, beta 3)", rows=rows)
+    return dict(study="subdivision", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid, FP64 form "
+                f"(order {presets.FP64_2D['taylor_order']}, beta {presets.FP64_2D['beta']})", rows=rows)
 
 
 def disagreement(grid=1024, bins=10):
@@ -105,7 +107,7 @@ def disagreement(grid=1024, bins=10):
     frac = ref - np.floor(ref)
     rows = []
     for order, beta in ((0, 2.0), (1, 2.0), (2, 2.0), (2, 4.0), (12, 3.0)):
-        m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order))
+        m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1))
         w, _ = _run(m, qd, reps=1)
         m.close()
         bad = np.rint(w) != np.rint(ref)
@@ -125,7 +127,7 @@ def overlap(grid=512):
         qd = _dev(q)
         ref, _ = _reference(curves, qd)
         for order, beta in ((0, 2.0), (2, 2.0), (12, 3.0)):
-            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order))
+            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1))
             w, _ = _run(m, qd, reps=1)
             m.close()
             err = np.abs(w - ref)
