@@ -76,6 +76,7 @@ class _Slot:
     bytes: int = 0
     out_w: object = None
     out_in: object = None
+    keep: tuple = ()                  # device buffers held until the event completes
 
 
 class Server:
@@ -254,7 +255,7 @@ class Server:
         s.offsets = offsets
         s.bytes = nbytes
         s.out_w, s.out_in = h_w, h_in
-        s.keep = (d_pts, d_w, d_in)     # device buffers live until the event completes
+        s.keep = (d_pts, d_w, d_in)
         self.in_flight_bytes += nbytes
         self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
         self.launches += 1
@@ -273,7 +274,7 @@ class Server:
                 finished += 1
         self.in_flight_bytes -= s.bytes
         s.busy = False
-        s.pieces, s.offsets, s.keep = [], [], None
+        s.pieces, s.offsets, s.keep = [], [], ()
         s.bytes = 0
         return finished
 
