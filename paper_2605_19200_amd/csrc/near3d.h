@@ -34,8 +34,8 @@ constexpr int kRadialGL = 12;    // nodes per radial piece (two or three pieces)
 constexpr int kMaxPanelsSide = 40;
 
 struct QuadTables {
-    double gx8[kOuterGL], gw8[kOuterGL];
-    double gx12[kRadialGL], gw12[kRadialGL];
+    double gxo[kOuterGL], gwo[kOuterGL];
+    double gxr[kRadialGL], gwr[kRadialGL];
 };
 
 
@@ -176,16 +176,16 @@ GWN_HD inline double radial(const QuadTables &Q, const double *__restrict__ h, d
         const double a = cuts[piece], b = cuts[piece + 1];
 #pragma unroll 1
         for (int i = 0; i < kRadialGL; ++i) {
-            const double x = a + (b - a) * Q.gx12[i];
+            const double x = a + (b - a) * Q.gxr[i];
             double tau, wt;
             if (uni) {
                 tau = x;
-                wt = (b - a) * Q.gw12[i];
+                wt = (b - a) * Q.gwr[i];
             } else {
                 // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
                 const double em = expm1(mu * x), ie = 1.0 / (1.0 + em);
                 tau = eps * 0.5 * (em + em * ie);
-                wt = eps * mu * 0.5 * (1.0 + em + ie) * (b - a) * Q.gw12[i];
+                wt = eps * mu * 0.5 * (1.0 + em + ie) * (b - a) * Q.gwr[i];
             }
             HomEval e;
             hom_eval(h, cu + tau * ru, cv + tau * rv, qx, qy, qz, e);
@@ -210,7 +210,7 @@ GWN_HD inline double graded_panels(const QuadTables &Q, double a, double b, doub
             double hi = side == 0 ? fmin(end, lo + w) : fmax(end, lo - w);
             if (k == kMaxPanelsSide - 1) hi = end;
             const double pa = fmin(lo, hi), pb = fmax(lo, hi), len = pb - pa;
-            for (int i = 0; i < kOuterGL; ++i) total += len * Q.gw8[i] * f(pa + len * Q.gx8[i]);
+            for (int i = 0; i < kOuterGL; ++i) total += len * Q.gwo[i] * f(pa + len * Q.gxo[i]);
             lo = hi;
             if (k > 0) w *= 2.0;
         }

@@ -412,8 +412,8 @@ static hipError_t ensure_tables()
     std::lock_guard<std::mutex> lk(g_tab_mu);
     if (dev >= 0 && dev < 64 && g_tab_ready[dev]) return hipSuccess;
     QuadTables t;
-    gauss_legendre01(kOuterGL, t.gx8, t.gw8);
-    gauss_legendre01(kRadialGL, t.gx12, t.gw12);
+    gauss_legendre01(kOuterGL, t.gxo, t.gwo);
+    gauss_legendre01(kRadialGL, t.gxr, t.gwr);
     e = hipMemcpyToSymbol(HIP_SYMBOL(c_quad), &t, sizeof t);
     if (e == hipSuccess && dev >= 0 && dev < 64) g_tab_ready[dev] = true;
     return e;

@@ -30,6 +30,7 @@ def test_every_declared_symbol_is_exported():
 def test_default_params():
     p = G.gwn_default_params()
     assert p.beta == 2.0 and p.taylor_order == 2 and p.max_diag_frac == 0.1 and p.gl_nodes == 10
+    assert p.leaf_far == 1 and p.reserved == 0
 
 
 def host_params(**kw):
@@ -82,7 +83,12 @@ def test_set_params_validation():
     with pytest.raises(G.GwnError):
         G.gwn_set_params(h, p)
     p.taylor_order = 1
+    p.leaf_far = 2
+    with pytest.raises(G.GwnError):
+        G.gwn_set_params(h, p)
+    p.leaf_far = 0
     p.beta = 8.0
     G.gwn_set_params(h, p)
+    assert G.gwn_get_params(h).leaf_far == 0
     assert G.gwn_get_params(h).beta == 8.0 and G.gwn_get_params(h).taylor_order == 1
     G.gwn_free(h)
