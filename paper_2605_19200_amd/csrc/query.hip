@@ -561,6 +561,17 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     std::vector<const Model *> models;
     T.n_seg = (int32_t)(s1 - s0);
     const int64_t row0 = segs[s0].q_begin;
+    // A 3D launch of fewer than 2^18 queries spreads them over up to 4096
+    // waves (at least 8 queries each): scattered queries share few nodes, so
+    // a wave's cost grows with its number of queries, and more waves keep
+    // more of the 1024 SIMDs busy.  Each query's value does not depend on
+    // its wave mates, so results are the same at any spread.
+    int64_t n_all = 0;
+    for (size_t k = s0; k < s1; ++k) n_all += segs[k].q_end - segs[k].q_begin;
+    int32_t qpw = 64;
+    if (dim == 3)
+        while (qpw > 8 && (int64_t)(qpw / 2) * 4096 >= n_all) qpw /= 2;
+    T.qpw = qpw;
     int64_t q = 0;
     int32_t wv = 0;
     for (size_t k = s0; k < s1; ++k) {
@@ -579,7 +590,7 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
         T.woff[j] = wv;
         const int64_t cnt = segs[k].q_end - segs[k].q_begin;
         q += cnt;
-        wv += (int32_t)((cnt + 63) / 64);
+        wv += (int32_t)((cnt + qpw - 1) / qpw);
     }
     T.qoff[T.n_seg] = q;
     T.woff[T.n_seg] = wv;

@@ -286,9 +286,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     if (wave >= T.n_waves) return;
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
-    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * 64 + lane;
+    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + lane;
     const int64_t slot = (int64_t)wave * 64 + lane;
-    const bool valid = pos < T.qoff[s + 1];
+    const bool valid = lane < T.qpw && pos < T.qoff[s + 1];
     const bool act = valid && (!RECLASS || NS.need[slot]);
     const uint64_t mask = __ballot(act);
     if (!mask) return;
@@ -332,9 +332,9 @@ __global__ __launch_bounds__(kBlock) void k_near3d(LaunchTable T, const int32_t 
     if (wave >= T.n_waves) return;
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
-    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * 64 + lane;
+    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + lane;
     const int64_t slot = (int64_t)wave * 64 + lane;
-    const bool valid = pos < T.qoff[s + 1];
+    const bool valid = lane < T.qpw && pos < T.qoff[s + 1];
     const bool act = valid && (!RECLASS || NS.need[slot]);
     if (!__ballot(act)) return;
     const int row = act ? perm[pos] : 0;
