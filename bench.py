@@ -75,6 +75,40 @@ def measured_traffic():
         return None
 
 
+def bench_small(calls: int = 256) -> dict:
+    """The small case (star loop of 64 rational cubics, 4096 queries), which
+    is bound by launch latency: one call's wall time, and the throughput of
+    `calls` calls issued back to back on one stream."""
+    import torch
+    from paper_2605_19200_amd import gwn as G
+    from paper_2605_19200_amd import presets
+    from paper_2605_19200_amd import workloads as W
+
+    curves, q = W.config1()
+    pts = torch.from_numpy(q).cuda()
+    m = G.Model(curves, presets.params(presets.FP64_2D))
+    out = torch.empty(q.shape[0], dtype=torch.float64, device="cuda")
+    ins = torch.empty(q.shape[0], dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        G.gwn_query(m.h, pts, out, ins)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(20):
+        t = time.perf_counter()
+        G.gwn_query(m.h, pts, out, ins)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+    t = time.perf_counter()
+    for _ in range(calls):
+        G.gwn_query(m.h, pts, out, ins)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    m.close()
+    return {"workload": f"star loop: {curves.n} rational cubics, {q.shape[0]} queries, FP64 form",
+            "call_ms_median": float(np.median(lat) * 1e3), "back_to_back_calls": calls,
+            "back_to_back_queries_per_s": calls * q.shape[0] / dt}
+
+
 def bench3d(steps: int = 1) -> dict:
     """3D side measurement: the bodies scene (4096 trimmed bicubic patches)
     on its 128^3 grid, FP64 and mixed forms, one timed pass each."""
@@ -298,6 +332,9 @@ def main():
     served = None if args.no_served else served_benchmark()
     served_all = None if args.no_served else served_benchmark(n_requests=200, kinds=("2d", "3d"), exp3d=(3.0, 4.0))
     side3d = None if args.no_3d else bench3d()
+    small = bench_small()
+    print(f"[bench] star loop: {small['call_ms_median']:.3f} ms per call, "
+          f"{small['back_to_back_queries_per_s']:.3e} q/s back to back", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -344,6 +381,7 @@ def main():
         "served": served,
         "served_2d_3d": served_all,
         "3d": side3d,
+        "small_case": small,
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic(),

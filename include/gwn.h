@@ -238,10 +238,10 @@ gwn_status gwn_query_counters(gwn_handle h, const double *points, int64_t n, int
                               void *stream);
 
 /* Memory accounting: bytes resident on the device for this model, and device
- * scratch bytes needed per query by gwn_query / gwn_query_batch.  A 3D launch
- * of fewer than 2^18 queries spreads them over up to 4096 waves, which takes
- * at most 4096 x 64 per-query slots (about 72 MB) in place of the per-query
- * figure. */
+ * scratch bytes needed per query by gwn_query / gwn_query_batch.  A launch
+ * of fewer than 2^18 queries spreads them over up to 4096 waves; in 3D that
+ * takes at most 4096 x 64 per-query slots of the near-field pass (about
+ * 72 MB) in place of the per-query figure. */
 gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_scratch);
 
 /* Host-side inspection of a built model (also for host-only handles).  Copies

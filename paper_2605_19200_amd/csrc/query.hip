@@ -435,8 +435,8 @@ __device__ __forceinline__ void query2d_body(const LaunchTable &T, const double 
         s = uniform_i(lo);
     }
     const DevModel &M = T.models[T.seg_model[s]];
-    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * 64 + lane;
-    const bool valid = pos < T.qoff[s + 1];
+    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + lane;
+    const bool valid = lane < T.qpw && pos < T.qoff[s + 1];
     const int row = valid ? perm[pos] : 0;
     const double qx = valid ? pts[2 * (int64_t)row] : 0.0;
     const double qy = valid ? pts[2 * (int64_t)row + 1] : 0.0;
@@ -561,7 +561,7 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     std::vector<const Model *> models;
     T.n_seg = (int32_t)(s1 - s0);
     const int64_t row0 = segs[s0].q_begin;
-    // A 3D launch of fewer than 2^18 queries spreads them over up to 4096
+    // A launch of fewer than 2^18 queries spreads them over up to 4096
     // waves (at least 8 queries each): scattered queries share few nodes, so
     // a wave's cost grows with its number of queries, and more waves keep
     // more of the 1024 SIMDs busy.  Each query's value does not depend on
@@ -569,8 +569,7 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     int64_t n_all = 0;
     for (size_t k = s0; k < s1; ++k) n_all += segs[k].q_end - segs[k].q_begin;
     int32_t qpw = 64;
-    if (dim == 3)
-        while (qpw > 8 && (int64_t)(qpw / 2) * 4096 >= n_all) qpw /= 2;
+    while (qpw > 8 && (int64_t)(qpw / 2) * 4096 >= n_all) qpw /= 2;
     T.qpw = qpw;
     int64_t q = 0;
     int32_t wv = 0;
@@ -601,10 +600,15 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     double *ow = out_gwn ? out_gwn + row0 : nullptr;
     uint8_t *oi = out_inside ? out_inside + row0 : nullptr;
 
-    // scratch: keys[2n] (u64), vals[2n] (i32), sort temp
+    // scratch: keys[2n] (u64), vals[2n] (i32), sort temp.  A small launch
+    // sorts on the top 24 key bits only (segment and the coarse Morton
+    // levels, far finer than its waves): fewer radix passes, fewer kernel
+    // launches, and no effect on any value.
+    const int sort_lo = n < (1 << 16) ? 30 : 0;
     size_t temp_bytes = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                                      (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 54, stream);
+                                                      (int32_t *)nullptr, (int32_t *)nullptr, (int)n, sort_lo, 54,
+                                                      stream);
     if (e != hipSuccess) return hip_err(e, "radix sort sizing", err);
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t b_keys = al(sizeof(uint64_t) * n), b_vals = al(sizeof(int32_t) * n);
@@ -621,7 +625,8 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     hipLaunchKernelGGL(k_keys, dim3(grid_q), dim3(kBlock), 0, stream, T, dim, pts, k_in, v_in, n);
     e = hipGetLastError();
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k_in, k_out, v_in, v_out, (int)n, 0, 54, stream);
+        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k_in, k_out, v_in, v_out, (int)n, sort_lo, 54,
+                                               stream);
     if (e != hipSuccess) st = hip_err(e, "key/sort launch", err);
     if (!st) {
         hipEvent_t ev0;

@@ -15,7 +15,7 @@ constexpr int kMaxBisectIter = 16384;
 struct LaunchTable {
     int32_t n_seg;
     int32_t n_waves;
-    int32_t qpw;        // queries per wave (64; 8..64 for small 3D launches)
+    int32_t qpw;        // queries per wave (64; 8..64 for small launches)
     int32_t pad;
     int32_t seg_model[kMaxSeg];
     int32_t woff[kMaxSeg + 1];
