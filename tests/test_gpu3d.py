@@ -120,12 +120,12 @@ def test_config3_fp64_sampled(cfg3):
 
 def test_config3_full_grid_subset_consistent(cfg3):
     """The full 128^3 launch gives the same values as the sampled call, and
-    no query of the grid hits a stack or near-field slot limit (NaN)."""
+    no query of the grid hits a stack or near-field slot limit (NaN).  (The
+    holed bodies are not closed, so w is not confined to [0, 1].)"""
     P, q, qs, ref = cfg3
     m = G.Model(P, presets.params(presets.FP64_3D))
     w_full, _ = run(m, q)
     assert np.all(np.isfinite(w_full))
-    assert np.all((w_full > -1e-6) & (w_full < 1 + 1e-6))   # disjoint closed bodies: w in [0, 1]
     idx = W.Rng(44, "s3").permutation(q.shape[0])[:96]
     assert np.array_equal(w_full[idx], run(m, q[idx])[0])
     check(w_full[idx], (w_full[idx] >= 0.5).astype(np.uint8), ref[:96])
