@@ -36,6 +36,26 @@ def _compile(src: str) -> str:
     return out
 
 
+EXAMPLE = os.path.join(HERE, "examples", "circle")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compile the plain C client of the C ABI (examples/circle.c) with the
+    host C compiler against include/gwn.h and the library just built."""
+    cc = os.environ.get("CC", "gcc")
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(HERE, "..", "include"), "-I", os.path.join(ROCM, "include"),
+           EXAMPLE + ".c", "-L", HERE, "-lgwn", "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", EXAMPLE]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {EXAMPLE}")
+    return EXAMPLE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
@@ -48,6 +68,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_example(verbose)
     return LIB
 
 

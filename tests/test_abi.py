@@ -92,3 +92,18 @@ def test_set_params_validation():
     assert G.gwn_get_params(h).leaf_far == 0
     assert G.gwn_get_params(h).beta == 8.0 and G.gwn_get_params(h).taylor_order == 1
     G.gwn_free(h)
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/gwn.h compiles as C99 on its own (no C++ or HIP types)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "t.c"
+    src.write_text('#include "gwn.h"\nint main(void) { gwn_params p; gwn_default_params(&p); return p.gl_nodes == 10 ? 0 : 1; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I",
+                        os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
