@@ -423,7 +423,9 @@ __device__ __forceinline__ void query2d_body(const LaunchTable &T, const double 
 {
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int wave = blockIdx.x * kWavesPerBlock + w;
+    // runs of 4 blocks per XCD for the FP64 kernel, 16 for the mixed one
+    // (each measured fastest for its kernel)
+    const int wave = xcd_block<(MIXED ? 16 : 4)>() * kWavesPerBlock + w;
     if (wave >= T.n_waves) return;
     int s = 0;
     {

@@ -46,6 +46,11 @@ __device__ __forceinline__ void ctr_add(Ctr &c, int k, long long v) { c.v[k] += 
 // (at most kNearSlots; more sets the overflow flag and gives NaN).
 constexpr int kNearSlots = 64;
 
+// Runs of 16 blocks per XCD (see xcd_block); both 3D passes must map
+// blocks to waves the same way, since the near-field pass reads the
+// traversal's per-slot scratch.
+constexpr int kXcdRun3 = 16;
+
 struct NearScratch {
     double *part;      // [n_waves * 64] solid angle of the far field and node-set leaves
     int32_t *cnt;      // [n_waves * 64] near leaves met by the traversal
@@ -282,7 +287,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     __shared__ StackLDS S;
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int wave = blockIdx.x * kWavesPerBlock + w;
+    const int wave = xcd_block<kXcdRun3>() * kWavesPerBlock + w;
     if (wave >= T.n_waves) return;
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_near3d(LaunchTable T, const int32_t 
 {
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int wave = blockIdx.x * kWavesPerBlock + w;
+    const int wave = xcd_block<kXcdRun3>() * kWavesPerBlock + w;
     if (wave >= T.n_waves) return;
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];

@@ -36,6 +36,25 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 }
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroup -> sorted-query range.  The dispatcher deals workgroups to the 8
+// XCDs round robin (block b runs on XCD b % 8), so with the identity map an
+// XCD's L2 serves waves from the whole range.  Handing each XCD runs of C
+// consecutive blocks, the runs themselves dealt round robin, keeps C
+// neighbouring regions' tree nodes in one L2 while the XCDs still share out
+// cheap and expensive regions evenly (one contiguous eighth per XCD was far
+// slower: the cost per wave varies strongly across a scene).  Blocks past
+// the last whole round of 8 C keep their own index.  A bijection on
+// [0, gridDim.x); values do not depend on it.
+template <int C>
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int full = nb / (8 * C) * (8 * C);
+    if (b >= full) return b;
+    const int x = b % 8, i = b / 8;
+    return ((i / C) * 8 + x) * C + i % C;
+}
+
 struct StackLDS {
     int node[kWavesPerBlock][kStackDepth];
     unsigned long long mask[kWavesPerBlock][kStackDepth];
