@@ -326,14 +326,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 // one by one in that order, so its result does not depend on its wave or
 // batch mates.  Mixed form, first pass: lanes with |w - 0.5| < band are
 // flagged for the FP64 re-evaluation instead of written.
+// One wave per workgroup: at one wave per SIMD (register bound) a workgroup
+// of four waves holds a whole CU until its slowest wave ends, and the waves'
+// pair counts differ widely; single-wave workgroups let each SIMD take the
+// next wave as soon as its own is done.
 template <bool COUNT, bool RECLASS>
-__global__ __launch_bounds__(kBlock) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
-                                                   const double *__restrict__ pts, double *__restrict__ out_w,
-                                                   uint8_t *__restrict__ out_in, long long *counters)
+__global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
+                                               const double *__restrict__ pts, double *__restrict__ out_w,
+                                               uint8_t *__restrict__ out_in, long long *counters)
 {
-    const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int wave = xcd_block<kXcdRun3>() * kWavesPerBlock + w;
+    const int wave = xcd_block<kXcdRun3 * kWavesPerBlock>();
     if (wave >= T.n_waves) return;
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
@@ -453,19 +456,20 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
     bool any_mixed = false;
     for (int j = 0; j < T.n_seg; ++j) any_mixed |= T.models[T.seg_model[j]].precision == GWN_MIXED;
     const dim3 g(grid), b(kBlock);
+    const dim3 gn(T.n_waves), bn(64);   // k_near3d: one wave per workgroup
     if (counters) {
         hipLaunchKernelGGL((k_trav3d<true, false>), g, b, 0, stream, T, pts, perm, NS, counters);
-        hipLaunchKernelGGL((k_near3d<true, false>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+        hipLaunchKernelGGL((k_near3d<true, false>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
         if (any_mixed) {
             hipLaunchKernelGGL((k_trav3d<true, true>), g, b, 0, stream, T, pts, perm, NS, counters);
-            hipLaunchKernelGGL((k_near3d<true, true>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+            hipLaunchKernelGGL((k_near3d<true, true>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
         }
     } else {
         hipLaunchKernelGGL((k_trav3d<false, false>), g, b, 0, stream, T, pts, perm, NS, counters);
-        hipLaunchKernelGGL((k_near3d<false, false>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+        hipLaunchKernelGGL((k_near3d<false, false>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
         if (any_mixed) {
             hipLaunchKernelGGL((k_trav3d<false, true>), g, b, 0, stream, T, pts, perm, NS, counters);
-            hipLaunchKernelGGL((k_near3d<false, true>), g, b, 0, stream, T, perm, NS, pts, out_w, out_in,
+            hipLaunchKernelGGL((k_near3d<false, true>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in,
                                counters);
         }
     }
