@@ -44,14 +44,17 @@ KERNEL_SOURCES = ["query.hip", "query_common.h", "gwn_internal.h"]
 
 def kernel_source_hash() -> str:
     """Hash of the 2D kernel's sources with comments and blank space removed
-    (a comment edit does not invalidate the recorded counters)."""
+    (a comment edit does not invalidate the recorded counters), and of the
+    FP64 parameter set the timed launch runs with."""
     import hashlib
     import re
+    from paper_2605_19200_amd import presets
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2605_19200_amd", "csrc", f)) as fh:
             text = re.sub(r"//[^\n]*", "", fh.read())
         h.update(" ".join(text.split()).encode())
+    h.update(repr(sorted(presets.FP64_2D.items())).encode())
     return h.hexdigest()[:16]
 
 
@@ -365,6 +368,7 @@ def main():
         "config": {"workload": "2D SVG-like drawing: 200 nested/overlapping loops, "
                                f"{curves.n} rational Bezier curves (degree 2-3), {args.grid}x{args.grid} grid",
                    "queries": n, "curves": curves.n, "beta": presets.FP64_2D["beta"],
+                   "far_tol": presets.FP64_2D.get("far_tol", 0.0),
                    "taylor_order": presets.FP64_2D["taylor_order"],
                    "max_diag_frac": presets.FP64_2D.get("max_diag_frac", 0.1), "leaves": n_leaves,
                    "build_s": round(build_s, 3)},

@@ -230,6 +230,56 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
             }
         }
     }
+    // Truncation data of each cluster for the error-budgeted far test, in
+    // the node's scaled variables a' = (a - c) / r, b' = (b - c) / r: the
+    // scaled moments m_k / r^(k+1) = (b' - a') s'_k / (k + 1) up to
+    // kTailOrder2D, the scaled chord length and rho = R / r.
+    {
+        const int nn = (int)m.tree.nodes.size();
+        std::vector<int> end(nn);
+        for (int i = nn - 1; i >= 0; --i) {
+            const HostNode &nd = m.tree.nodes[i];
+            end[i] = nd.is_leaf ? i + 1 : end[nd.right];
+        }
+        m.tail2.assign((size_t)nn * kTailStride2D, 0.0);
+        std::vector<double> acc(2 * (kTailOrder2D + 1));
+        for (int i = 0; i < nn; ++i) {
+            const HostNode &nd = m.tree.nodes[i];
+            if (nd.is_leaf || !(nd.r > 0)) continue;
+            const double ir = 1.0 / nd.r;
+            std::fill(acc.begin(), acc.end(), 0.0);
+            double len = 0.0;
+            for (int j = i; j < end[i]; ++j) {
+                const HostNode &lf = m.tree.nodes[j];
+                if (!lf.is_leaf) continue;
+                const double *hh = leaves[lf.leaf].h;
+                const double ar = (hh[0] / hh[2] - nd.c[0]) * ir, ai = (hh[1] / hh[2] - nd.c[1]) * ir;
+                const double br = (hh[9] / hh[11] - nd.c[0]) * ir, bi = (hh[10] / hh[11] - nd.c[1]) * ir;
+                const double dr = br - ar, di = bi - ai;
+                len += std::hypot(dr, di);
+                double sr = 1.0, si = 0.0, pr = 1.0, pi = 0.0;
+                for (int k = 0; k <= kTailOrder2D; ++k) {
+                    if (k > 0) {
+                        const double npr = pr * ar - pi * ai, npi = pr * ai + pi * ar;
+                        pr = npr; pi = npi;
+                        const double nsr = br * sr - bi * si + pr, nsi = br * si + bi * sr + pi;
+                        sr = nsr; si = nsi;
+                    }
+                    acc[2 * k] += (dr * sr - di * si) / (k + 1);
+                    acc[2 * k + 1] += (dr * si + di * sr) / (k + 1);
+                }
+            }
+            double R2 = 0.0;
+            for (int a = 0; a < 2; ++a) {
+                const double e = std::max(nd.c[a] - nd.lo[a], nd.hi[a] - nd.c[a]);
+                R2 += e * e;
+            }
+            double *t = &m.tail2[(size_t)i * kTailStride2D];
+            for (int k = 0; k <= kTailOrder2D; ++k) t[k] = std::hypot(acc[2 * k], acc[2 * k + 1]);
+            t[kTailOrder2D + 1] = len;
+            t[kTailOrder2D + 2] = std::sqrt(R2) * ir;
+        }
+    }
     // leaves in BVH leaf order (order of appearance in the DFS layout)
     m.leaf_src.clear();
     m.leaf_h.clear();
@@ -245,6 +295,38 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
             m.leaf_degree.push_back(leaves[src].degree);
         }
     return GWN_OK;
+}
+
+// Truncation error of the order-p chord expansion of a cluster at
+// x = r / ||q - c||, in turns.  With the scaled moments mt_k = m_k / r^(k+1)
+// the omitted terms are sum_{k>p} mt_k v^(k+1), |v| = x (Sec. 3.1, the
+// series of Eq. taylor carried on in complex form).  The terms up to
+// kTailOrder2D are taken with their exact magnitudes; beyond, every chord
+// point lies within R = rho r of the centroid, so |mt_k| <= (L / r) rho^k and
+// the rest sums to at most (L / r) rho^(J+1) x^(J+2) / (1 - rho x).  The bound
+// grows with x, so the largest admissible x is found by bisection.
+double far_beta2d(const double *tail, int order, double tol)
+{
+    const int J = kTailOrder2D;
+    const double len = tail[J + 1], rho = tail[J + 2];
+    auto bound = [&](double x) -> double {
+        if (rho * x >= 1.0) return HUGE_VAL;
+        double s = 0.0, xp = std::pow(x, order + 2);
+        for (int k = order + 1; k <= J; ++k) {
+            s += tail[k] * xp;
+            xp *= x;
+        }
+        s += len * std::pow(rho, J + 1) * xp / (1.0 - rho * x);
+        return s / (2.0 * kPi);
+    };
+    double lo = 0.0, hi = 0.5;       // beta >= 2: the chord substitution holds outside the AABB
+    if (bound(hi) <= tol) return 2.0;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (bound(mid) <= tol) lo = mid;
+        else hi = mid;
+    }
+    return lo > 0.0 ? 1.0 / lo : HUGE_VAL;
 }
 
 }  // namespace gwn

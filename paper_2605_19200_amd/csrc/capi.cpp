@@ -46,6 +46,7 @@ extern "C" void gwn_default_params(gwn_params *p)
     p->eps_q = 1e-10;
     p->leaf_far = 1;
     p->reserved = 0;
+    p->far_tol = 0.0;
 }
 
 static gwn_status check_query_params(int dim, const gwn_params *p)
@@ -56,12 +57,14 @@ static gwn_status check_query_params(int dim, const gwn_params *p)
     if (dim == 2 && (p->beta < 2.0 || p->beta_mixed < 2.0))
         return fail(GWN_EINVAL, "2D requires beta >= 2 (chord substitution needs q outside every accepted AABB)");
     if (p->taylor_order < 0 || p->taylor_order > (dim == 2 ? kMaxOrder2D : kMaxOrder3D))
-        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..8 in 2D" : "taylor_order must be 0..6 in 3D");
+        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..12 in 2D" : "taylor_order must be 0..6 in 3D");
     if (p->precision != GWN_FP64 && p->precision != GWN_MIXED) return fail(GWN_EINVAL, "bad precision");
     if (!(p->reclass_band >= 0) || !std::isfinite(p->reclass_band)) return fail(GWN_EINVAL, "bad reclass_band");
     if (!(p->near_ratio >= 0) || !std::isfinite(p->near_ratio)) return fail(GWN_EINVAL, "bad near_ratio");
     if (!(p->eps_q > 0)) return fail(GWN_EINVAL, "eps_q must be > 0");
     if (p->leaf_far != 0 && p->leaf_far != 1) return fail(GWN_EINVAL, "leaf_far must be 0 or 1");
+    if (!(p->far_tol >= 0) || !std::isfinite(p->far_tol)) return fail(GWN_EINVAL, "far_tol must be finite and >= 0");
+    if (dim == 3 && p->far_tol != 0.0) return fail(GWN_EINVAL, "far_tol applies to 2D models only");
     return GWN_OK;
 }
 
@@ -83,7 +86,8 @@ void refresh_dev_params(Model &m)
     m.dev.dim = m.dim;
     m.dev.order = p.taylor_order;
     m.dev.precision = p.precision;
-    m.dev.beta2 = p.beta * p.beta;
+    // error-budgeted 2D far test: the cluster radii carry their own factor
+    m.dev.beta2 = (m.dim == 2 && p.far_tol > 0.0) ? 1.0 : p.beta * p.beta;
     m.dev.beta2_mixed = p.beta_mixed * p.beta_mixed;
     m.dev.band = p.reclass_band;
     for (int a = 0; a < 3; ++a) {
@@ -147,6 +151,11 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> 
             }
         } else {
             t.a[0] = n.c[0]; t.a[1] = n.c[1]; t.a[2] = n.r2; t.a[3] = h.r;
+            if (m.params.far_tol > 0.0 && h.r > 0.0) {
+                // (beta_c r)^2, compared with ||q - c||^2 at beta2 = 1
+                const double bc = far_beta2d(&m.tail2[i * kTailStride2D], m.params.taylor_order, m.params.far_tol);
+                t.a[2] = std::isfinite(bc) ? (bc * h.r) * (bc * h.r) : HUGE_VAL;
+            }
             t.f[0] = n.fc[0]; t.f[1] = n.fc[1]; t.f[2] = n.fr2; t.f[3] = (float)h.r;
         }
         t.right = n.right;
@@ -362,9 +371,26 @@ extern "C" gwn_status gwn_set_params(gwn_handle h, const gwn_params *params)
     p.near_ratio = params->near_ratio;
     p.leaf_far = params->leaf_far;
     p.eps_q = params->eps_q;
+    p.far_tol = params->far_tol;
     gwn_status s = check_query_params(h->m.dim, &p);
     if (s) return s;
+    const gwn_params old = h->m.params;
     h->m.params = p;
+    const bool radii = h->m.dim == 2 && (p.far_tol != old.far_tol ||
+                                        (p.far_tol > 0.0 && p.taylor_order != old.taylor_order));
+    if (radii && h->m.d_arena) {
+        // the far radii live in the node records: rewrite them once no
+        // launch can still read them
+        std::vector<Node2> n2; std::vector<Hot2> h2; std::vector<Prim2> p2;
+        pack2d(h->m, n2, h2, p2);
+        hipError_t e = hipSetDevice(h->m.device);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy((void *)h->m.dev.hot, h2.data(), h2.size() * sizeof(Hot2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            h->m.params = old;
+            return fail(GWN_EHIP, std::string("far radii update: ") + hipGetErrorString(e));
+        }
+    }
     refresh_dev_params(h->m);
     return GWN_OK;
 }
@@ -528,6 +554,20 @@ extern "C" gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64
         width = 2 * (kMaxOrder2D + 1);
         items = (int64_t)m.tree.nodes.size();
         buf.assign(m.cmom2.begin(), m.cmom2.end());
+        break;
+    }
+    case GWN_I_FARBETA: {
+        if (d != 2) return fail(GWN_EINVAL, "far-field factors are inspected for 2D models only");
+        width = 1;
+        items = (int64_t)m.tree.nodes.size();
+        buf.assign(items, 0.0);
+        for (int64_t i = 0; i < items; ++i) {
+            const HostNode &n = m.tree.nodes[i];
+            if (n.is_leaf) continue;
+            buf[i] = m.params.far_tol > 0.0 && n.r > 0.0
+                         ? far_beta2d(&m.tail2[i * kTailStride2D], m.params.taylor_order, m.params.far_tol)
+                         : m.params.beta;
+        }
         break;
     }
     case GWN_I_MULTIPOLE: {

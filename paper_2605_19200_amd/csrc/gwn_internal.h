@@ -31,6 +31,12 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // hi.y).  The float fields mirror c, r2 and the scaled m_0..m_11 for the
 // FP32 pass.
 constexpr int kMaxOrder2D = 12;
+// Error-budgeted far test (2D): per internal node, the magnitudes of the
+// scaled moments |m_k| / r^(k+1) for k = 0..kTailOrder2D, then L / r (L the
+// total chord length) and rho = R / r (R the largest distance from the
+// centroid to the node's AABB); see far_beta2d.
+constexpr int kTailOrder2D = 32;
+constexpr int kTailStride2D = kTailOrder2D + 3;
 constexpr int kMaxOrder3D = 6;   // harmonic degree <= 7, see multipole3d.h
 constexpr int kMaxL3 = kMaxOrder3D + 1;   // highest solid-harmonic degree
 constexpr int kMpoleTerms = 35;           // (l, m) with 1 <= l <= 7, 0 <= m <= l
@@ -205,6 +211,7 @@ struct Model {
     std::vector<double> leaf_h;       // 12 (2D) or 64 (3D) doubles per leaf
     std::vector<int32_t> leaf_degree; // 2D original degree
     std::vector<double> cmom2;        // 2D: per node 2*(kMaxOrder2D+1) centred complex moments
+    std::vector<double> tail2;        // 2D: per node kTailStride2D doubles (far_beta2d)
     // 3D only
     std::vector<Trim3> trims;
     std::vector<int32_t> leaf_trim_begin, leaf_trim_count;
@@ -223,6 +230,11 @@ struct Model {
 };
 
 // builders (host)
+// Far-field factor of one 2D cluster under an error budget: the smallest
+// beta >= 2 for which the truncation error of its order-`order` expansion
+// is at most `tol` (in turns) wherever ||q - c|| > beta r.  +inf when no
+// beta meets the budget.
+double far_beta2d(const double *tail, int order, double tol);
 gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, std::string &err);
 gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, std::string &err);
 // Bezier extraction of 2D NURBS curves (nurbs.cpp); false with err set on

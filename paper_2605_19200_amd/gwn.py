@@ -20,7 +20,8 @@ GWN_OK, GWN_EINVAL, GWN_ENOMEM, GWN_EHIP, GWN_EUNSUPPORTED, GWN_EOVERFLOW = rang
 GWN_FP64, GWN_MIXED = 0, 1
 COUNTER_NAMES = ["nodes", "far", "leaves", "leaf_fast", "pieces", "angles", "reclass", "overflow"]
 GWN_NCOUNTERS = len(COUNTER_NAMES)
-GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX, GWN_I_MULTIPOLE = range(7)
+(GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX, GWN_I_MULTIPOLE,
+ GWN_I_FARBETA) = range(8)
 
 EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
             "gwn_get_params", "gwn_query",
@@ -39,7 +40,7 @@ class gwn_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("reclass_band", ctypes.c_double), ("max_diag_frac", ctypes.c_double),
                 ("eps_on", ctypes.c_double), ("gl_nodes", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("near_ratio", ctypes.c_double), ("eps_q", ctypes.c_double), ("leaf_far", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("far_tol", ctypes.c_double)]
 
 
 class gwn_curves2d(ctypes.Structure):
@@ -210,7 +211,7 @@ def gwn_model_bytes(h):
 
 _WIDTH = {GWN_I_SUMMARY: lambda d: 8, GWN_I_LEAVES: lambda d: 13 if d == 2 else 65, GWN_I_NODES: lambda d: 13,
           GWN_I_MOMENTS: lambda d: d + d * d + d ** 3, GWN_I_UNCENTERED: lambda d: d + d * d + d ** 3,
-          GWN_I_COMPLEX: lambda d: 26, GWN_I_MULTIPOLE: lambda d: 72}
+          GWN_I_COMPLEX: lambda d: 26, GWN_I_MULTIPOLE: lambda d: 72, GWN_I_FARBETA: lambda d: 1}
 
 
 def gwn_inspect(h, what: int) -> np.ndarray:

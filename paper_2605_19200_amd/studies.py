@@ -4,6 +4,8 @@ after the paper's experiments on its own datasets:
   order_beta     max |dw| and time against (order, beta)      (Sec. 4.2, Fig. beta_sweep)
   subdivision    leaves, build and query time, error against the subdivision
                  threshold                                     (Sec. 4.1)
+  far_tol        error, time and node visits against the error budget of the
+                 per-cluster far test                          (Sec. 5, future work)
   disagreement   grid points whose rounded w differs from the rounded
                  reference, binned by the reference's fractional part
                                                                (Sec. 4.3)
@@ -11,7 +13,9 @@ after the paper's experiments on its own datasets:
                  error and misclassifications against k       (Sec. 4.3, Fig. overlap_demo)
 
 The order, disagreement and overlap studies use the paper's 10 % subdivision
-threshold; the subdivision study runs the FP64 preset's order and beta.
+threshold and one far-field factor for all clusters; the subdivision study
+runs the FP64 preset (order 12, error-budgeted far test); far_tol sweeps
+the budget of that test.
 The reference is the same engine with the far field switched off (beta =
 1e8: every leaf evaluated directly), whose agreement with the FP64 oracle is
 a GPU test of its own.  Each study prints one JSON line to stdout and its
@@ -55,7 +59,7 @@ def _run(model, qd, reps=3):
 
 
 def _reference(curves, qd):
-    m = G.Model(curves, presets.params(presets.FP64_2D, beta=1e8))
+    m = G.Model(curves, presets.params(presets.FP64_2D, beta=1e8, far_tol=0.0))
     w, ms = _run(m, qd, reps=1)
     m.close()
     return w, ms
@@ -69,7 +73,7 @@ def order_beta(grid=1024):
     rows = []
     for order in (0, 1, 2, 4, 8, 12):
         for beta in (2.0, 3.0, 4.0, 6.0, 8.0, 16.0, 32.0, 64.0):
-            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1))
+            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1, far_tol=0.0))
             w, ms = _run(m, qd)
             m.close()
             err = np.abs(w - ref)
@@ -97,7 +101,25 @@ def subdivision(grid=1024):
                          ms=round(ms, 3), max_abs_dw=float(np.abs(w - ref).max())))
         _log(f"subdivision: {frac} -> {leaves} leaves, {ms:.2f} ms")
     return dict(study="subdivision", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid, FP64 form "
-                f"(order {presets.FP64_2D['taylor_order']}, beta {presets.FP64_2D['beta']})", rows=rows)
+                f"(order {presets.FP64_2D['taylor_order']}, far_tol {presets.FP64_2D['far_tol']})", rows=rows)
+
+
+def far_tol(grid=1024):
+    curves, q = W.config2(grid=grid)
+    qd = _dev(q)
+    ref, _ = _reference(curves, qd)
+    rows = []
+    for tol in (0.0, 3e-9, 1e-8, 2e-8, 5e-8, 1e-7):
+        m = G.Model(curves, presets.params(presets.FP64_2D, far_tol=tol))
+        w, ms = _run(m, qd)
+        nodes = m.counters(qd)["nodes"]
+        m.close()
+        err = np.abs(w - ref)
+        rows.append(dict(far_tol=tol, max_abs_dw=float(err.max()), p99_abs_dw=float(np.quantile(err, 0.99)),
+                         ms=round(ms, 3), node_visits=int(nodes)))
+        _log(f"far_tol: {tol} -> {ms:.2f} ms")
+    return dict(study="far_tol", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid, order "
+                f"{presets.FP64_2D['taylor_order']} (far_tol 0: uniform beta {presets.FP64_2D['beta']})", rows=rows)
 
 
 def disagreement(grid=1024, bins=10):
@@ -107,7 +129,7 @@ def disagreement(grid=1024, bins=10):
     frac = ref - np.floor(ref)
     rows = []
     for order, beta in ((0, 2.0), (1, 2.0), (2, 2.0), (2, 4.0), (12, 3.0)):
-        m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1))
+        m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1, far_tol=0.0))
         w, _ = _run(m, qd, reps=1)
         m.close()
         bad = np.rint(w) != np.rint(ref)
@@ -127,7 +149,7 @@ def overlap(grid=512):
         qd = _dev(q)
         ref, _ = _reference(curves, qd)
         for order, beta in ((0, 2.0), (2, 2.0), (12, 3.0)):
-            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1))
+            m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1, far_tol=0.0))
             w, _ = _run(m, qd, reps=1)
             m.close()
             err = np.abs(w - ref)
@@ -139,7 +161,8 @@ def overlap(grid=512):
                 rows=rows)
 
 
-STUDIES = dict(order_beta=order_beta, subdivision=subdivision, disagreement=disagreement, overlap=overlap)
+STUDIES = dict(order_beta=order_beta, subdivision=subdivision, far_tol=far_tol, disagreement=disagreement,
+               overlap=overlap)
 
 
 def main(argv=None):

@@ -43,7 +43,7 @@ def cfg1(oracle):
 
 def test_config1_all_direct(cfg1):
     curves, q, ref = cfg1
-    m = G.Model(curves, presets.params(presets.FP64_2D, beta=1e8))
+    m = G.Model(curves, presets.params(presets.FP64_2D, beta=1e8, far_tol=0.0))
     w, ins = run(m, q)
     check(w, ins, ref, tol=1e-11)
 
@@ -77,13 +77,13 @@ def test_degenerate_models(oracle):
     assert np.all(w == 0)
     # one curve: the root is a leaf
     one = W.Curves2D.from_list([W.circle_curves((0, 0), 1.0, 3)[0]])
-    m = G.Model(one, presets.params(presets.FP64_2D, beta=1e8))
+    m = G.Model(one, presets.params(presets.FP64_2D, beta=1e8, far_tol=0.0))
     w, ins = run(m, q)
     check(w, ins, oracle.gwn2d(one, q), tol=1e-12)
     # straight segments, square corners/edges (direct values 0.25 / 0.5)
     sq = W.Curves2D.from_list(W.square_trim())
     qs = np.array([[0, 0], [1, 1], [0.5, 0], [1, 0.3], [0.5, 0.5], [1.5, 0.5]], float)
-    m = G.Model(sq, presets.params(presets.FP64_2D, beta=1e8))
+    m = G.Model(sq, presets.params(presets.FP64_2D, beta=1e8, far_tol=0.0))
     w, _ = run(m, qs)
     assert np.allclose(w, [0.25, 0.25, 0.5, 0.5, 1.0, 0.0], atol=1e-14)
 
@@ -92,7 +92,7 @@ def test_circle_boundary_and_near(oracle):
     circ = W.Curves2D.from_list(W.circle_curves((0.1, 0.2), 0.9, 4))
     th = W.Rng(22, "th").uniform(200, 0, 2 * math.pi)
     on = np.stack([0.1 + 0.9 * np.cos(th), 0.2 + 0.9 * np.sin(th)], 1)
-    exact = G.Model(circ, presets.params(presets.FP64_2D, beta=1e8))   # every leaf direct
+    exact = G.Model(circ, presets.params(presets.FP64_2D, beta=1e8, far_tol=0.0))   # every leaf direct
     prod = G.Model(circ, presets.params(presets.FP64_2D))
     for m, tol in [(exact, 1e-12), (prod, TOL)]:
         w, _ = run(m, on)
@@ -206,7 +206,8 @@ def test_overlapping_polygons(oracle, k):
     w, ins = run(m, q)
     check(w, ins, ref)
     if k == 16:
-        m0 = G.Model(curves, presets.params(presets.FP64_2D, beta=2.0, taylor_order=0, max_diag_frac=0.1))
+        m0 = G.Model(curves, presets.params(presets.FP64_2D, beta=2.0, taylor_order=0, max_diag_frac=0.1,
+                                                   far_tol=0.0))
         w0, _ = run(m0, q)
         assert np.abs(w0 - ref).max() > 0.05   # the order-0 error grows with the overlap
 
@@ -236,7 +237,7 @@ def test_error_decreases_with_order(cfg2):
     """At a fixed far-field factor the error drops with each added order of
     the expansion (Sec. 4.2: about an order of magnitude per order)."""
     curves, q, ref = cfg2
-    m = G.Model(curves, presets.params(presets.FP64_2D, beta=6.0, taylor_order=0))
+    m = G.Model(curves, presets.params(presets.FP64_2D, beta=6.0, taylor_order=0, far_tol=0.0))
     errs = []
     for order in range(0, 9):
         m.set(taylor_order=order)
@@ -253,3 +254,32 @@ def test_counters(cfg1):
     c = m.counters(dev(q))
     assert c["leaves"] > 0 and c["nodes"] > 0 and c["overflow"] == 0
     assert c["leaf_fast"] <= c["leaves"] and c["angles"] >= c["leaf_fast"]
+
+
+def test_far_tol_budget_and_set_params(cfg2):
+    """Error-budgeted far test: within the FP64 bound against the oracle,
+    no slower in node visits than the uniform factor at the same accuracy,
+    and switching it on or off through gwn_set_params (which rewrites the
+    cluster radii on the device) gives bit for bit the results of a model
+    built with that setting."""
+    curves, q, ref = cfg2
+    uni = G.Model(curves, presets.params(presets.FP64_2D, far_tol=0.0))
+    bud = G.Model(curves, presets.params(presets.FP64_2D, far_tol=1e-8))
+    w_uni, _ = run(uni, q)
+    w_bud, ins = run(bud, q)
+    check(w_bud, ins, ref)
+    qd = dev(q)
+    assert bud.counters(qd)["nodes"] < uni.counters(qd)["nodes"]
+    uni.set(far_tol=1e-8)
+    w, _ = run(uni, q)
+    assert np.array_equal(w, w_bud)
+    uni.set(taylor_order=8)
+    w8, _ = run(uni, q)
+    fresh8 = G.Model(curves, presets.params(presets.FP64_2D, far_tol=1e-8, taylor_order=8))
+    assert np.array_equal(w8, run(fresh8, q)[0])
+    check(w8, (w8 >= 0.5).astype(np.uint8), ref)
+    uni.set(far_tol=0.0, taylor_order=12)
+    w, _ = run(uni, q)
+    assert np.array_equal(w, w_uni)
+    for m in (uni, bud, fresh8):
+        m.close()

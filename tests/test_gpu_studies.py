@@ -38,3 +38,13 @@ def test_subdivision_and_disagreement_run():
     assert rows[12, 3.0]["disagreements"] == 0
     assert rows[0, 2.0]["disagreements"] >= rows[2, 2.0]["disagreements"]
     assert sum(rows[0, 2.0]["hist"]) == rows[0, 2.0]["disagreements"]
+
+
+def test_far_tol_study_trends():
+    out = studies.far_tol(grid=128)
+    rows = {r["far_tol"]: r for r in out["rows"]}
+    budgets = sorted(t for t in rows if t > 0)
+    # a looser budget accepts clusters sooner: fewer node visits, larger error
+    visits = [rows[t]["node_visits"] for t in budgets]
+    assert visits == sorted(visits, reverse=True)
+    assert rows[1e-8]["max_abs_dw"] < 1e-6 and rows[1e-8]["node_visits"] < rows[0.0]["node_visits"]
