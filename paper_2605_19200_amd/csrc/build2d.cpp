@@ -20,12 +20,31 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "gwn_internal.h"
 
 namespace gwn {
 
 namespace {
+
+// f(i) for i in [0, n) on up to 16 host threads, interleaved so that the
+// large subtrees near the top of the DFS order spread over all threads.
+template <class F>
+void for_nodes(int n, F f)
+{
+    const int nt = std::max(1, std::min<int>({16, (int)std::thread::hardware_concurrency(), n / 256 + 1}));
+    if (nt == 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+            for (int i = t; i < n; i += nt) f(i);
+        });
+    for (auto &th : pool) th.join();
+}
 
 struct Cubic {
     double h[12];  // (wx, wy, w) x 4
@@ -204,9 +223,9 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
             end[i] = nd.is_leaf ? i + 1 : end[nd.right];
         }
         m.cmom2.assign((size_t)nn * 2 * K, 0.0);
-        for (int i = 0; i < nn; ++i) {
+        for_nodes(nn, [&](int i) {
             const HostNode &nd = m.tree.nodes[i];
-            if (nd.is_leaf) continue;
+            if (nd.is_leaf) return;
             double *out = &m.cmom2[(size_t)i * 2 * K];
             for (int j = i; j < end[i]; ++j) {
                 const HostNode &lf = m.tree.nodes[j];
@@ -228,7 +247,7 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
                     out[2 * k + 1] += (dr * si + di * sr) / (k + 1);
                 }
             }
-        }
+        });
     }
     // Truncation data of each cluster for the error-budgeted far test, in
     // the node's scaled variables a' = (a - c) / r, b' = (b - c) / r: the
@@ -242,12 +261,11 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
             end[i] = nd.is_leaf ? i + 1 : end[nd.right];
         }
         m.tail2.assign((size_t)nn * kTailStride2D, 0.0);
-        std::vector<double> acc(2 * (kTailOrder2D + 1));
-        for (int i = 0; i < nn; ++i) {
+        for_nodes(nn, [&](int i) {
             const HostNode &nd = m.tree.nodes[i];
-            if (nd.is_leaf || !(nd.r > 0)) continue;
+            if (nd.is_leaf || !(nd.r > 0)) return;
             const double ir = 1.0 / nd.r;
-            std::fill(acc.begin(), acc.end(), 0.0);
+            double acc[2 * (kTailOrder2D + 1)] = {};
             double len = 0.0;
             for (int j = i; j < end[i]; ++j) {
                 const HostNode &lf = m.tree.nodes[j];
@@ -278,7 +296,7 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
             for (int k = 0; k <= kTailOrder2D; ++k) t[k] = std::hypot(acc[2 * k], acc[2 * k + 1]);
             t[kTailOrder2D + 1] = len;
             t[kTailOrder2D + 2] = std::sqrt(R2) * ir;
-        }
+        });
     }
     // leaves in BVH leaf order (order of appearance in the DFS layout)
     m.leaf_src.clear();

@@ -117,3 +117,13 @@ def test_rejected_in_3d():
     P = W.config3(grid=4)[0]
     with pytest.raises(G.GwnError):
         G.gwn_build3d(P, G.gwn_default_params(device=-1, far_tol=1e-8, max_diag_frac=10.0))
+
+
+def test_loose_budget_floors_at_two_and_tight_budget_is_finite():
+    curves = W.star_loop(seed=3, n_curves=64)
+    for tol, check in ((1.0, lambda b: np.all(b == 2.0)), (1e-15, lambda b: np.all(np.isfinite(b)) and np.all(b > 2.0))):
+        h = _host(curves, taylor_order=12, far_tol=tol, max_diag_frac=0.05)
+        nodes = G.gwn_inspect(h, G.GWN_I_NODES)
+        fb = G.gwn_inspect(h, G.GWN_I_FARBETA)[:, 0]
+        G.gwn_free(h)
+        assert check(fb[nodes[:, 0] == 0]), (tol, fb[nodes[:, 0] == 0].min(), fb[nodes[:, 0] == 0].max())
