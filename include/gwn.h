@@ -15,7 +15,7 @@
  * moments of Sec. 3.1, Karras BVH, moment up-sweep and centering) and upload
  * the result to one GPU.  gwn_query runs the query phase of Alg. 1 on the
  * GPU: BVH traversal, the far-field test ||q - centroid|| > beta * radius,
- * the Taylor approximation of Eq. taylor (order 0..12 in 2D, 0..6 in 3D)
+ * the Taylor approximation of Eq. taylor (order 0..16 in 2D, 0..6 in 3D)
  * for far clusters, and
  * direct evaluation (Sec. 3.3) of every leaf reached.
  *
@@ -119,7 +119,7 @@ typedef struct {
     double beta_mixed;     /* Q: far-field factor of the FP32 pass of the mixed
                               form (default 4)                               */
     int32_t taylor_order;  /* Q: expansion order of Eq. taylor; default 2
-                              (Sec. 4.2).  2D: 0..12, 3D: 0..6 -- orders above
+                              (Sec. 4.2).  2D: 0..16, 3D: 0..6 -- orders above
                               2 carry the same expansion further (2D: exact
                               chord moments in complex form; 3D: solid
                               harmonics, see GWN_I_MULTIPOLE)                */
@@ -279,7 +279,7 @@ gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_s
  *   GWN_I_UNCENTERED per node: the uncentered moments (same layout)
  *   GWN_I_COMPLEX   2D only, per node: the centred complex moments
  *                   m_k = integral over the cluster's chords of (z - c)^k dz,
- *                   k = 0..12, as (re, im) pairs -- 26 doubles (zero for leaves)
+ *                   k = 0..16, as (re, im) pairs -- 34 doubles (zero for leaves)
  *   GWN_I_MULTIPOLE 3D only, per node: 1/r (r = AABB half diagonal), 0, then
  *                   for l = 1..7, m = 0..l the moments
  *                   N_l^m = -integral n . conj(grad R_l^m(x - c)) dA scaled

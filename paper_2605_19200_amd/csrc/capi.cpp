@@ -57,7 +57,7 @@ static gwn_status check_query_params(int dim, const gwn_params *p)
     if (dim == 2 && (p->beta < 2.0 || p->beta_mixed < 2.0))
         return fail(GWN_EINVAL, "2D requires beta >= 2 (chord substitution needs q outside every accepted AABB)");
     if (p->taylor_order < 0 || p->taylor_order > (dim == 2 ? kMaxOrder2D : kMaxOrder3D))
-        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..12 in 2D" : "taylor_order must be 0..6 in 3D");
+        return fail(GWN_EINVAL, dim == 2 ? "taylor_order must be 0..16 in 2D" : "taylor_order must be 0..6 in 3D");
     if (p->precision != GWN_FP64 && p->precision != GWN_MIXED) return fail(GWN_EINVAL, "bad precision");
     if (!(p->reclass_band >= 0) || !std::isfinite(p->reclass_band)) return fail(GWN_EINVAL, "bad reclass_band");
     if (!(p->near_ratio >= 0) || !std::isfinite(p->near_ratio)) return fail(GWN_EINVAL, "bad near_ratio");

@@ -25,12 +25,16 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 // 2D node, three 128-byte lines.  Internal: centroid, squared AABB half
 // diagonal r^2 and the complex form of the centred moments, stored scaled
 // as m_k / r^(k+1) with m_k = integral (z - c)^k dz over the cluster's
-// chords (re, im pairs, k = 0..12), so the far field is a series in
+// chords (re, im pairs, k = 0..16), so the far field is a series in
 // r / (q - c), whose modulus is below 1 / beta for an accepted cluster.
 // Leaf: m[0..3] holds the leaf's control-point AABB (lo.x, lo.y, hi.x,
-// hi.y).  The float fields mirror c, r2 and the scaled m_0..m_11 for the
+// hi.y).  The float fields mirror c, r2 and the scaled m_0..m_15 for the
 // FP32 pass.
-constexpr int kMaxOrder2D = 12;
+constexpr int kMaxOrder2D = 16;
+// The FP32 pass has a second unrolled instance at order 11 (FP32 rounding
+// dominates beyond), used by the mixed form at FP64 order 12..14; the FP64
+// pass has one at order 12 beside kMaxOrder2D.
+constexpr int kMixedOrder2D = 11;
 // Error-budgeted far test (2D): per internal node, the magnitudes of the
 // scaled moments |m_k| / r^(k+1) for k = 0..kTailOrder2D, then L / r (L the
 // total chord length) and rho = R / r (R the largest distance from the
@@ -52,7 +56,7 @@ struct alignas(128) Node2 {
     float fm[2 * kMaxOrder2D];
     float pad[1];
 };
-static_assert(sizeof(Node2) == 384, "Node2 must be three 128-byte lines");
+static_assert(sizeof(Node2) == 512, "Node2 must be four 128-byte lines");
 
 // 2D traversal record, 64 bytes, one array of them beside the Node2 array
 // (same DFS index).  It holds everything a node test or a leaf's fast path

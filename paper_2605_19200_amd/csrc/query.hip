@@ -381,6 +381,8 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                     if (far)
                         acc += M.order >= kMaxOrder2D - 1
                                    ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, ff[3], nodes[cur].fm)
+                               : M.order >= kMixedOrder2D
+                                   ? (double)taylor2d_fixed<float, kMixedOrder2D>(dx, dy, d2, ff[3], nodes[cur].fm)
                                    : (double)taylor2d<float>(dx, dy, d2, ff[3], nodes[cur].fm, M.order);
                 } else {
                     const double dx = qx - bb[0], dy = qy - bb[1];
@@ -389,6 +391,8 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                     if (far)
                         acc += M.order == kMaxOrder2D
                                    ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, bb[3], nodes[cur].m)
+                               : M.order == kMixedOrder2D + 1
+                                   ? taylor2d_fixed<double, kMixedOrder2D + 1>(dx, dy, d2, bb[3], nodes[cur].m)
                                    : taylor2d<double>(dx, dy, d2, bb[3], nodes[cur].m, M.order);
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;

@@ -211,7 +211,7 @@ def gwn_model_bytes(h):
 
 _WIDTH = {GWN_I_SUMMARY: lambda d: 8, GWN_I_LEAVES: lambda d: 13 if d == 2 else 65, GWN_I_NODES: lambda d: 13,
           GWN_I_MOMENTS: lambda d: d + d * d + d ** 3, GWN_I_UNCENTERED: lambda d: d + d * d + d ** 3,
-          GWN_I_COMPLEX: lambda d: 26, GWN_I_MULTIPOLE: lambda d: 72, GWN_I_FARBETA: lambda d: 1}
+          GWN_I_COMPLEX: lambda d: 34, GWN_I_MULTIPOLE: lambda d: 72, GWN_I_FARBETA: lambda d: 1}
 
 
 def gwn_inspect(h, what: int) -> np.ndarray:

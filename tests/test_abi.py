@@ -79,7 +79,7 @@ def test_set_params_validation():
     curves, _ = W.config1()
     h = G.gwn_build2d(curves, host_params())
     p = G.gwn_get_params(h)
-    p.taylor_order = 13
+    p.taylor_order = 17
     with pytest.raises(G.GwnError):
         G.gwn_set_params(h, p)
     p.taylor_order = 1

@@ -278,7 +278,7 @@ def test_far_tol_budget_and_set_params(cfg2):
     fresh8 = G.Model(curves, presets.params(presets.FP64_2D, far_tol=1e-8, taylor_order=8))
     assert np.array_equal(w8, run(fresh8, q)[0])
     check(w8, (w8 >= 0.5).astype(np.uint8), ref)
-    uni.set(far_tol=0.0, taylor_order=12)
+    uni.set(far_tol=0.0, taylor_order=presets.FP64_2D["taylor_order"])
     w, _ = run(uni, q)
     assert np.array_equal(w, w_uni)
     for m in (uni, bud, fresh8):
