@@ -71,7 +71,7 @@ def order_beta(grid=1024):
     ref, ref_ms = _reference(curves, qd)
     _log(f"order_beta: reference {ref_ms:.1f} ms")
     rows = []
-    for order in (0, 1, 2, 4, 8, 12):
+    for order in (0, 1, 2, 4, 8, 12, 16):
         for beta in (2.0, 3.0, 4.0, 6.0, 8.0, 16.0, 32.0, 64.0):
             m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1, far_tol=0.0))
             w, ms = _run(m, qd)
