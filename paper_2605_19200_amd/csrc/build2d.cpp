@@ -213,7 +213,12 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
     // cancellation of short chords.  (Summing uncentered moments and shifting
     // them, as done for the Cartesian order-2 moments, loses about
     // k log10(|c| / r) digits at order k.)  A DFS subtree is the contiguous
-    // node range [i, end_i).
+    // node range [i, end_i).  Then the truncation data of each cluster for the
+    // error-budgeted far test, in the node's scaled variables
+    // a' = (a - c) / r, b' = (b - c) / r: the scaled moments
+    // m_k / r^(k+1) = (b' - a') s'_k / (k + 1) up to kTailOrder2D, the scaled
+    // chord length and rho = R / r.  A model built for a device computes both
+    // there (moments2d.hip); a host-only model on up to 16 host threads.
     {
         const int nn = (int)m.tree.nodes.size();
         const int K = kMaxOrder2D + 1;
@@ -222,81 +227,85 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
             const HostNode &nd = m.tree.nodes[i];
             end[i] = nd.is_leaf ? i + 1 : end[nd.right];
         }
-        m.cmom2.assign((size_t)nn * 2 * K, 0.0);
-        for_nodes(nn, [&](int i) {
-            const HostNode &nd = m.tree.nodes[i];
-            if (nd.is_leaf) return;
-            double *out = &m.cmom2[(size_t)i * 2 * K];
-            for (int j = i; j < end[i]; ++j) {
-                const HostNode &lf = m.tree.nodes[j];
-                if (!lf.is_leaf) continue;
-                const double *hh = leaves[lf.leaf].h;
-                double ar = hh[0] / hh[2] - nd.c[0], ai = hh[1] / hh[2] - nd.c[1];
-                double br = hh[9] / hh[11] - nd.c[0], bi = hh[10] / hh[11] - nd.c[1];
-                double dr = br - ar, di = bi - ai;
-                // s_k = sum_{j<=k} b^j a^{k-j}: s_0 = 1, s_k = b s_{k-1} + a^k
-                double sr = 1.0, si = 0.0, pr = 1.0, pi = 0.0;  // p = a^k
-                for (int k = 0; k < K; ++k) {
-                    if (k > 0) {
-                        double npr = pr * ar - pi * ai, npi = pr * ai + pi * ar;
-                        pr = npr; pi = npi;
-                        double nsr = br * sr - bi * si + pr, nsi = br * si + bi * sr + pi;
-                        sr = nsr; si = nsi;
-                    }
-                    out[2 * k] += (dr * sr - di * si) / (k + 1);
-                    out[2 * k + 1] += (dr * si + di * sr) / (k + 1);
+        if (p->device >= 0 && nn > 1) {
+            std::vector<double> chord_ends;
+            chord_ends.reserve(4 * (size_t)nl);
+            for (const HostNode &nd : m.tree.nodes)
+                if (nd.is_leaf) {
+                    const double *hh = leaves[nd.leaf].h;
+                    chord_ends.insert(chord_ends.end(), {hh[0] / hh[2], hh[1] / hh[2], hh[9] / hh[11], hh[10] / hh[11]});
                 }
-            }
-        });
-    }
-    // Truncation data of each cluster for the error-budgeted far test, in
-    // the node's scaled variables a' = (a - c) / r, b' = (b - c) / r: the
-    // scaled moments m_k / r^(k+1) = (b' - a') s'_k / (k + 1) up to
-    // kTailOrder2D, the scaled chord length and rho = R / r.
-    {
-        const int nn = (int)m.tree.nodes.size();
-        std::vector<int> end(nn);
-        for (int i = nn - 1; i >= 0; --i) {
-            const HostNode &nd = m.tree.nodes[i];
-            end[i] = nd.is_leaf ? i + 1 : end[nd.right];
+            const gwn_status s = moments2d_device(p->device, m.tree.nodes, end, chord_ends, m.cmom2, m.tail2, err);
+            if (s != GWN_OK) return s;
+        } else {
+            m.cmom2.assign((size_t)nn * 2 * K, 0.0);
+            for_nodes(nn, [&](int i) {
+                const HostNode &nd = m.tree.nodes[i];
+                if (nd.is_leaf) return;
+                double *out = &m.cmom2[(size_t)i * 2 * K];
+                for (int j = i; j < end[i]; ++j) {
+                    const HostNode &lf = m.tree.nodes[j];
+                    if (!lf.is_leaf) continue;
+                    const double *hh = leaves[lf.leaf].h;
+                    double ar = hh[0] / hh[2] - nd.c[0], ai = hh[1] / hh[2] - nd.c[1];
+                    double br = hh[9] / hh[11] - nd.c[0], bi = hh[10] / hh[11] - nd.c[1];
+                    double dr = br - ar, di = bi - ai;
+                    // s_k = sum_{j<=k} b^j a^{k-j}: s_0 = 1, s_k = b s_{k-1} + a^k
+                    double sr = 1.0, si = 0.0, pr = 1.0, pi = 0.0;  // p = a^k
+                    for (int k = 0; k < K; ++k) {
+                        if (k > 0) {
+                            double npr = pr * ar - pi * ai, npi = pr * ai + pi * ar;
+                            pr = npr; pi = npi;
+                            double nsr = br * sr - bi * si + pr, nsi = br * si + bi * sr + pi;
+                            sr = nsr; si = nsi;
+                        }
+                        out[2 * k] += (dr * sr - di * si) / (k + 1);
+                        out[2 * k + 1] += (dr * si + di * sr) / (k + 1);
+                    }
+                }
+            });
+            m.tail2.assign((size_t)nn * kTailStride2D, 0.0);
+            for_nodes(nn, [&](int i) {
+                const HostNode &nd = m.tree.nodes[i];
+                if (nd.is_leaf || !(nd.r > 0)) return;
+                const double ir = 1.0 / nd.r;
+                double acc[2 * (kTailOrder2D + 1)] = {};
+                double len = 0.0;
+                for (int j = i; j < end[i]; ++j) {
+                    const HostNode &lf = m.tree.nodes[j];
+                    if (!lf.is_leaf) continue;
+                    const double *hh = leaves[lf.leaf].h;
+                    const double ar = (hh[0] / hh[2] - nd.c[0]) * ir, ai = (hh[1] / hh[2] - nd.c[1]) * ir;
+                    const double br = (hh[9] / hh[11] - nd.c[0]) * ir, bi = (hh[10] / hh[11] - nd.c[1]) * ir;
+                    const double dr = br - ar, di = bi - ai;
+                    len += std::hypot(dr, di);
+                    double sr = 1.0, si = 0.0, pr = 1.0, pi = 0.0;
+                    for (int k = 0; k <= kTailOrder2D; ++k) {
+                        if (k > 0) {
+                            const double npr = pr * ar - pi * ai, npi = pr * ai + pi * ar;
+                            pr = npr; pi = npi;
+                            const double nsr = br * sr - bi * si + pr, nsi = br * si + bi * sr + pi;
+                            sr = nsr; si = nsi;
+                        }
+                        acc[2 * k] += (dr * sr - di * si) / (k + 1);
+                        acc[2 * k + 1] += (dr * si + di * sr) / (k + 1);
+                    }
+                }
+                double *t = &m.tail2[(size_t)i * kTailStride2D];
+                for (int k = 0; k <= kTailOrder2D; ++k) t[k] = std::hypot(acc[2 * k], acc[2 * k + 1]);
+                t[kTailOrder2D + 1] = len;
+            });
         }
-        m.tail2.assign((size_t)nn * kTailStride2D, 0.0);
-        for_nodes(nn, [&](int i) {
+        for (int i = 0; i < nn; ++i) {
             const HostNode &nd = m.tree.nodes[i];
-            if (nd.is_leaf || !(nd.r > 0)) return;
-            const double ir = 1.0 / nd.r;
-            double acc[2 * (kTailOrder2D + 1)] = {};
-            double len = 0.0;
-            for (int j = i; j < end[i]; ++j) {
-                const HostNode &lf = m.tree.nodes[j];
-                if (!lf.is_leaf) continue;
-                const double *hh = leaves[lf.leaf].h;
-                const double ar = (hh[0] / hh[2] - nd.c[0]) * ir, ai = (hh[1] / hh[2] - nd.c[1]) * ir;
-                const double br = (hh[9] / hh[11] - nd.c[0]) * ir, bi = (hh[10] / hh[11] - nd.c[1]) * ir;
-                const double dr = br - ar, di = bi - ai;
-                len += std::hypot(dr, di);
-                double sr = 1.0, si = 0.0, pr = 1.0, pi = 0.0;
-                for (int k = 0; k <= kTailOrder2D; ++k) {
-                    if (k > 0) {
-                        const double npr = pr * ar - pi * ai, npi = pr * ai + pi * ar;
-                        pr = npr; pi = npi;
-                        const double nsr = br * sr - bi * si + pr, nsi = br * si + bi * sr + pi;
-                        sr = nsr; si = nsi;
-                    }
-                    acc[2 * k] += (dr * sr - di * si) / (k + 1);
-                    acc[2 * k + 1] += (dr * si + di * sr) / (k + 1);
-                }
-            }
+            if (nd.is_leaf || !(nd.r > 0)) continue;
             double R2 = 0.0;
             for (int a = 0; a < 2; ++a) {
                 const double e = std::max(nd.c[a] - nd.lo[a], nd.hi[a] - nd.c[a]);
                 R2 += e * e;
             }
-            double *t = &m.tail2[(size_t)i * kTailStride2D];
-            for (int k = 0; k <= kTailOrder2D; ++k) t[k] = std::hypot(acc[2 * k], acc[2 * k + 1]);
-            t[kTailOrder2D + 1] = len;
-            t[kTailOrder2D + 2] = std::sqrt(R2) * ir;
-        });
+            m.tail2[(size_t)i * kTailStride2D + kTailOrder2D + 2] = std::sqrt(R2) / nd.r;
+        }
     }
     // leaves in BVH leaf order (order of appearance in the DFS layout)
     m.leaf_src.clear();

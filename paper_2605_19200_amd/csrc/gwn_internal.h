@@ -239,6 +239,13 @@ struct Model {
 // is at most `tol` (in turns) wherever ||q - c|| > beta r.  +inf when no
 // beta meets the budget.
 double far_beta2d(const double *tail, int order, double tol);
+// Chord moments of every 2D cluster on `device` (moments2d.hip): cmom2 and
+// tail2 as the host build lays them out, except tail2's rho entries, which
+// the caller fills.  chord_ends holds (ax, ay, bx, by) per leaf in DFS order;
+// end[i] is the end of node i's DFS subtree.
+gwn_status moments2d_device(int device, const std::vector<HostNode> &nodes, const std::vector<int> &end,
+                            const std::vector<double> &chord_ends, std::vector<double> &cmom2,
+                            std::vector<double> &tail2, std::string &err);
 gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, std::string &err);
 gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, std::string &err);
 // Bezier extraction of 2D NURBS curves (nurbs.cpp); false with err set on

@@ -283,3 +283,40 @@ def test_far_tol_budget_and_set_params(cfg2):
     assert np.array_equal(w, w_uni)
     for m in (uni, bud, fresh8):
         m.close()
+
+
+@pytest.mark.parametrize("which", ["star", "drawing"])
+def test_device_moments_match_host(which):
+    """A model built for a device computes its cluster moments and
+    truncation data there (one wave per cluster); a host-only build of the
+    same input sums them on the host.  Same tree, same values up to the
+    order of summation."""
+    curves = W.star_loop(seed=5) if which == "star" else W.config2(grid=4)[0]
+    hd = G.gwn_build2d(curves, presets.params(presets.FP64_2D))
+    hh = G.gwn_build2d(curves, presets.params(presets.FP64_2D, device=-1))
+    try:
+        nd, nh = G.gwn_inspect(hd, G.GWN_I_NODES), G.gwn_inspect(hh, G.GWN_I_NODES)
+        assert np.array_equal(nd, nh)
+        cd, ch = G.gwn_inspect(hd, G.GWN_I_COMPLEX), G.gwn_inspect(hh, G.GWN_I_COMPLEX)
+        # rounding scale of m_k: chord length L of the cluster times R^k,
+        # R = 2 r bounding |z - c| (closed loops cancel to ~0, so |m_k| itself
+        # is no scale)
+        lv = G.gwn_inspect(hh, G.GWN_I_LEAVES)[:, 1:].reshape(-1, 4, 3)
+        ln = np.hypot(lv[:, 3, 0] / lv[:, 3, 2] - lv[:, 0, 0] / lv[:, 0, 2],
+                      lv[:, 3, 1] / lv[:, 3, 2] - lv[:, 0, 1] / lv[:, 0, 2])
+        n = nh.shape[0]
+        end = np.zeros(n, dtype=np.int64)
+        for i in range(n - 1, -1, -1):
+            end[i] = i + 1 if nh[i, 0] else end[int(nh[i, 2])]
+        cum = np.concatenate([[0.0], np.cumsum(np.where(nh[:, 0] == 1, ln[nh[:, 1].astype(int) * (nh[:, 0] == 1)], 0.0))])
+        L = cum[end] - cum[np.arange(n)]
+        K = ch.shape[1] // 2
+        tol = 1e-13 * L[:, None] * (2 * nh[:, 6:7]) ** np.repeat(np.arange(K), 2)[None, :] + 1e-300
+        assert np.all(np.abs(cd - ch) <= tol), np.max(np.abs(cd - ch) / tol)
+        assert np.all(cd[nh[:, 0] == 1] == 0)
+        fd, fh = G.gwn_inspect(hd, G.GWN_I_FARBETA)[:, 0], G.gwn_inspect(hh, G.GWN_I_FARBETA)[:, 0]
+        internal = nh[:, 0] == 0
+        assert np.all(np.abs(fd[internal] - fh[internal]) <= 1e-9 * fh[internal])
+    finally:
+        G.gwn_free(hd)
+        G.gwn_free(hh)
