@@ -194,9 +194,16 @@ struct HostTree {
 // ConstructBVH, SumUncenteredMomentsUpTree, CenterMomentsInPlace).
 // leafU: n * nm uncentered moments, leafW: n centroid weights, leafWC: n * 3
 // weighted centroid sums.  Returns false with `err` set on failure.
+// device >= 0: the Morton codes, their sort and the child links run on that
+// device (lbvh_device); the tree is the same.
 bool build_tree(int dim, int n, const double *lo, const double *hi, const double *leafU,
                 const double *leafW, const double *leafWC, const double *model_lo,
-                const double *model_hi, HostTree &tree, std::string &err);
+                const double *model_hi, HostTree &tree, std::string &err, int device = -1);
+// Sorted leaf order and Karras child links (>= 0 internal, < 0 leaf at
+// sorted position -1 - x) of n >= 2 leaves, computed on `device`.
+bool lbvh_device(int device, int dim, int n, const double *lo, const double *hi, const double *model_lo,
+                 const double *model_hi, std::vector<int> &order, std::vector<int> &cl, std::vector<int> &cr,
+                 std::string &err);
 
 inline int n_moments(int dim) { return dim + dim * dim + dim * dim * dim; }
 

@@ -62,7 +62,7 @@ struct Karras {
 
 bool build_tree(int dim, int n, const double *lo, const double *hi, const double *leafU,
                 const double *leafW, const double *leafWC, const double *model_lo,
-                const double *model_hi, HostTree &tree, std::string &err)
+                const double *model_hi, HostTree &tree, std::string &err, int device)
 {
     tree.dim = dim;
     tree.nodes.clear();
@@ -70,47 +70,52 @@ bool build_tree(int dim, int n, const double *lo, const double *hi, const double
     const int nm = n_moments(dim);
     if (n <= 0) return true;
 
-    // Morton codes of leaf AABB centres, sorted (stable on leaf index).
-    std::vector<uint64_t> key(n);
-    for (int i = 0; i < n; ++i) {
-        uint64_t k = 0;
-        for (int a = 0; a < dim; ++a) {
-            double cc = 0.5 * (lo[3 * i + a] + hi[3 * i + a]);
-            uint64_t qv = quant(cc, model_lo[a], model_hi[a], dim == 2 ? 32 : 21);
-            k |= (dim == 2 ? spread2(qv) : spread3(qv)) << a;
-        }
-        key[i] = k;
-    }
     std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-    std::vector<uint64_t> code(n);
-    for (int i = 0; i < n; ++i) code[i] = key[order[i]];
-
-    // Karras: internal node i covers a key range and splits it at gamma.
-    // Children encoding: >= 0 internal index, < 0 leaf (-1 - sorted position).
     std::vector<int> cl(std::max(n - 1, 0)), cr(std::max(n - 1, 0));
-    Karras K{code, n};
-    for (int i = 0; i < n - 1; ++i) {
-        int d = (K.delta(i, i + 1) - K.delta(i, i - 1)) >= 0 ? 1 : -1;
-        int dmin = K.delta(i, i - d);
-        int lmax = 2;
-        while (K.delta(i, i + lmax * d) > dmin) lmax *= 2;
-        int l = 0;
-        for (int t = lmax / 2; t >= 1; t /= 2)
-            if (K.delta(i, i + (l + t) * d) > dmin) l += t;
-        int j = i + l * d;
-        int dnode = K.delta(i, j);
-        int s = 0;
-        for (int div = 2;; div *= 2) {
-            int t = (l + div - 1) / div;
-            if (K.delta(i, i + (s + t) * d) > dnode) s += t;
-            if (t <= 1) break;
+    if (device >= 0 && n > 1) {
+        // same codes, order and links, computed on the device (lbvh.hip)
+        if (!lbvh_device(device, dim, n, lo, hi, model_lo, model_hi, order, cl, cr, err)) return false;
+    } else {
+        // Morton codes of leaf AABB centres, sorted (stable on leaf index).
+        std::vector<uint64_t> key(n);
+        for (int i = 0; i < n; ++i) {
+            uint64_t k = 0;
+            for (int a = 0; a < dim; ++a) {
+                double cc = 0.5 * (lo[3 * i + a] + hi[3 * i + a]);
+                uint64_t qv = quant(cc, model_lo[a], model_hi[a], dim == 2 ? 32 : 21);
+                k |= (dim == 2 ? spread2(qv) : spread3(qv)) << a;
+            }
+            key[i] = k;
         }
-        int gamma = i + s * d + std::min(d, 0);
-        int a = std::min(i, j), b = std::max(i, j);
-        cl[i] = (a == gamma) ? -1 - gamma : gamma;
-        cr[i] = (b == gamma + 1) ? -1 - (gamma + 1) : gamma + 1;
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+        std::vector<uint64_t> code(n);
+        for (int i = 0; i < n; ++i) code[i] = key[order[i]];
+
+        // Karras: internal node i covers a key range and splits it at gamma.
+        // Children encoding: >= 0 internal index, < 0 leaf (-1 - sorted position).
+        Karras K{code, n};
+        for (int i = 0; i < n - 1; ++i) {
+            int d = (K.delta(i, i + 1) - K.delta(i, i - 1)) >= 0 ? 1 : -1;
+            int dmin = K.delta(i, i - d);
+            int lmax = 2;
+            while (K.delta(i, i + lmax * d) > dmin) lmax *= 2;
+            int l = 0;
+            for (int t = lmax / 2; t >= 1; t /= 2)
+                if (K.delta(i, i + (l + t) * d) > dmin) l += t;
+            int j = i + l * d;
+            int dnode = K.delta(i, j);
+            int s = 0;
+            for (int div = 2;; div *= 2) {
+                int t = (l + div - 1) / div;
+                if (K.delta(i, i + (s + t) * d) > dnode) s += t;
+                if (t <= 1) break;
+            }
+            int gamma = i + s * d + std::min(d, 0);
+            int a = std::min(i, j), b = std::max(i, j);
+            cl[i] = (a == gamma) ? -1 - gamma : gamma;
+            cr[i] = (b == gamma + 1) ? -1 - (gamma + 1) : gamma + 1;
+        }
     }
 
     // Depth-first pre-order layout.

@@ -295,8 +295,10 @@ def test_device_moments_match_host(which):
     hd = G.gwn_build2d(curves, presets.params(presets.FP64_2D))
     hh = G.gwn_build2d(curves, presets.params(presets.FP64_2D, device=-1))
     try:
+        # the device LBVH (codes, sort, child links) gives the host's tree
         nd, nh = G.gwn_inspect(hd, G.GWN_I_NODES), G.gwn_inspect(hh, G.GWN_I_NODES)
         assert np.array_equal(nd, nh)
+        assert np.array_equal(G.gwn_inspect(hd, G.GWN_I_LEAVES), G.gwn_inspect(hh, G.GWN_I_LEAVES))
         cd, ch = G.gwn_inspect(hd, G.GWN_I_COMPLEX), G.gwn_inspect(hh, G.GWN_I_COMPLEX)
         # rounding scale of m_k: chord length L of the cluster times R^k,
         # R = 2 r bounding |z - c| (closed loops cancel to ~0, so |m_k| itself

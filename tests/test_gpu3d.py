@@ -231,3 +231,19 @@ def test_stretched_patch_near_field(cfg3, oracle):
     m = G.Model(P, presets.params(presets.FP64_3D))
     w, ins = run(m, q)
     check(w, ins, oracle.gwn3d(P, q))
+
+
+def test_device_lbvh_matches_host():
+    """A model built for a device sorts its leaves and links the radix tree
+    there; the tree, the leaf order and the moments equal a host-only build
+    of the same patches exactly."""
+    P = W.bodies(3, [("sphere", np.array([0.0, 0.0, 0.0]), 1.0), ("torus", np.array([2.5, 0.3, 0.1]), 0.8)])
+    P = W.Patches3D.from_list([(cp, w, W.square_trim()) for cp, w in P])
+    hd = G.gwn_build3d(P, presets.params(presets.FP64_3D))
+    hh = G.gwn_build3d(P, presets.params(presets.FP64_3D, device=-1))
+    try:
+        for what in (G.GWN_I_NODES, G.GWN_I_LEAVES, G.GWN_I_MULTIPOLE):
+            assert np.array_equal(G.gwn_inspect(hd, what), G.gwn_inspect(hh, what)), what
+    finally:
+        G.gwn_free(hd)
+        G.gwn_free(hh)
