@@ -202,7 +202,7 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
         WC[3 * i + 2] = 0;
     }
     if (!build_tree(2, nl, LO.data(), HI.data(), U.data(), Wt.data(), WC.data(), m.lo, m.hi, m.tree, err, p->device))
-        return GWN_EINVAL;
+        return err.rfind("device BVH", 0) == 0 ? GWN_EHIP : GWN_EINVAL;
     if (m.tree.depth > kStackDepth) {
         err = "BVH depth " + std::to_string(m.tree.depth) + " exceeds the traversal stack";
         return GWN_EOVERFLOW;

@@ -418,7 +418,7 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         for (auto &th : pool) th.join();
     }
     if (!build_tree(3, nl, LO.data(), HI.data(), U.data(), Wt.data(), WC.data(), m.lo, m.hi, m.tree, err, p->device))
-        return GWN_EINVAL;
+        return err.rfind("device BVH", 0) == 0 ? GWN_EHIP : GWN_EINVAL;
     if (m.tree.depth > kStackDepth) {
         err = "BVH depth " + std::to_string(m.tree.depth) + " exceeds the traversal stack";
         return GWN_EOVERFLOW;
