@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "gwn_internal.h"
@@ -170,10 +171,31 @@ void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Query launches take their scratch (sort keys, permutation, near-field
+// pairs) from the device's default stream-ordered pool.  With the pool's
+// default release threshold of zero, every synchronisation hands the freed
+// scratch back to the driver and the next launch maps it again; keeping up
+// to kPoolKeepBytes cached removes that from each call.  Set once per device.
+constexpr uint64_t kPoolKeepBytes = 1ull << 30;
+
+static void keep_pool_scratch(int device)
+{
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (std::find(done.begin(), done.end(), device) != done.end()) return;
+    done.push_back(device);
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, device) != hipSuccess || !pool) return;
+    uint64_t keep = kPoolKeepBytes;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+}
+
 gwn_status upload_model(Model &m, std::string &err)
 {
     hipError_t e = hipSetDevice(m.device);
     if (e != hipSuccess) { err = std::string("hipSetDevice: ") + hipGetErrorString(e); return GWN_EHIP; }
+    keep_pool_scratch(m.device);
     // Arena: nodes | prims | trims | qnodes | mpole | fmpole | hot, each
     // 256-byte aligned (trims to fmpole are 3D only, hot 2D only).
     std::vector<Node2> n2; std::vector<Prim2> p2; std::vector<Hot2> h2;
