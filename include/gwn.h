@@ -220,7 +220,11 @@ gwn_status gwn_get_params(gwn_handle h, gwn_params *out);
  * (1 when w >= 0.5) or NULL.  n may be 0.  Asynchronous on `stream`.
  * Errors: GWN_EINVAL (NULL handle, n < 0, NULL buffers with n > 0, host-only
  * handle), GWN_EHIP, GWN_EOVERFLOW (reported by the NEXT call on the handle
- * after a kernel hit a stack limit; the affected outputs are NaN). */
+ * after a kernel hit a stack limit; the affected outputs are NaN).
+ * Scratch comes from the device's default stream-ordered pool (hipMallocAsync
+ * on `stream`, freed on it at the end of the call); building a model for a
+ * device raises that pool's release threshold to 1 GiB, process-wide, so the
+ * scratch stays mapped between calls. */
 gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
                      uint8_t *out_inside, void *stream);
 
