@@ -285,13 +285,21 @@ def test_far_tol_budget_and_set_params(cfg2):
         m.close()
 
 
-@pytest.mark.parametrize("which", ["star", "drawing"])
+def _duplicates():
+    """A circle plus 200 copies of one tiny segment: many equal leaf codes,
+    which the radix tree orders by position."""
+    seg = (np.array([[0.1, 0.1], [0.1001, 0.1]]), np.ones(2))
+    return W.Curves2D.from_list(W.circle_curves((0, 0), 1.0) + [seg] * 200)
+
+
+@pytest.mark.parametrize("which", ["star", "drawing", "duplicates"])
 def test_device_moments_match_host(which):
     """A model built for a device computes its cluster moments and
     truncation data there (one wave per cluster); a host-only build of the
     same input sums them on the host.  Same tree, same values up to the
     order of summation."""
-    curves = W.star_loop(seed=5) if which == "star" else W.config2(grid=4)[0]
+    curves = {"star": lambda: W.star_loop(seed=5), "drawing": lambda: W.config2(grid=4)[0],
+              "duplicates": _duplicates}[which]()
     hd = G.gwn_build2d(curves, presets.params(presets.FP64_2D))
     hh = G.gwn_build2d(curves, presets.params(presets.FP64_2D, device=-1))
     try:
