@@ -30,8 +30,19 @@
  * Direct value on the boundary: when q lies on a primitive, that primitive's
  * integral is taken as the (absolutely convergent) integral itself, which is
  * the mean of the two one-sided limits (0.5 at smooth points of a closed
- * boundary).  The grading floor eps_on keeps the quadrature from resolving a
- * spike narrower than eps_on, which yields that value.
+ * boundary).  When q is within eps_on of a primitive (2D: of the curve; 3D:
+ * of the patch's surface over its whole parameter square), the primitive's
+ * value is computed as the mean of its values at q + delta n and q - delta n,
+ * with n the unit normal at the foot point and delta = 1e3 eps_on.  At a
+ * point of the visible primitive that mean is the direct value; at a
+ * trimmed-away point of a patch the value is continuous across the surface,
+ * so the mean is the value itself.
+ *
+ * Non-convergence is never silent: panels that the adaptive rule accepts at
+ * a work limit with an error estimate above its tolerance are counted, and
+ * their estimates, scaled by the enclosing quadrature weights, give a bound
+ * on the unresolved part of each value (oracle_last_unconverged,
+ * oracle_last_errbound).
  *
  * Trimmed patches (3D): the visible region D of [0,1]^2 is bounded by closed
  * loops of rational trim curves (degree 1 or 2), outer loop counter-clockwise,
@@ -94,12 +105,34 @@ static void gl_init(void)
     gl_ready = 1;
 }
 
+/* Panels accepted only because a work limit was reached (MAX_SPLITS,
+ * MAX_DEPTH, or a panel too narrow to halve in FP64) while the error
+ * estimate still exceeded both acceptance tests.  Counted per thread and
+ * summed over the queries of each oracle_gwn2d / oracle_gwn3d call, so that a
+ * value the quadrature did not resolve is never silent. */
+static _Thread_local long long tl_unconverged = 0;
+static long long g_last_unconverged = 0;
+/* Error bound of those panels, carried to the final value: each one adds
+ * its estimate |l + r - whole| times the factor by which the enclosing
+ * quadratures scale its integral (the outer Gauss weights and |v'| of the
+ * nested 3D rule, tl_mult).  The panel evaluations that only serve error
+ * estimates are included, so the bound is conservative.  Reported per query
+ * in units of w; the largest of a call is kept. */
+static _Thread_local double tl_mult = 1.0;
+static _Thread_local double tl_errbound = 0.0;
+static double g_last_errbound = 0.0;
+
 typedef double (*fn1)(double, void *);
 
 static double gl_panel(fn1 f, void *ctx, double a, double b)
 {
     double c = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
-    for (int i = 0; i < GLN; ++i) s += gl_w[i] * f(c + h * gl_x[i], ctx);
+    const double saved = tl_mult;
+    for (int i = 0; i < GLN; ++i) {
+        tl_mult = saved * fabs(gl_w[i] * h);
+        s += gl_w[i] * f(c + h * gl_x[i], ctx);
+    }
+    tl_mult = saved;
     return s * h;
 }
 
@@ -108,7 +141,10 @@ static double gl_panel(fn1 f, void *ctx, double a, double b)
  * length) of the tolerance, or to `rel` relative (the roundoff level of the
  * integrand near a near-singular peak: forming H - q W loses ~|H|/|A| digits).  Work is bounded: at most
  * MAX_SPLITS bisections and a bisection depth of MAX_DEPTH per call. */
+#ifndef MAX_SPLITS
 #define MAX_SPLITS 2000
+#endif
+
 static double adapt(fn1 f, void *ctx, double a, double b, double tol, double rel)
 {
     if (!(b > a)) return 0.0;
@@ -123,8 +159,12 @@ static double adapt(fn1 f, void *ctx, double a, double b, double tol, double rel
         double l = gl_panel(f, ctx, pa, m), r = gl_panel(f, ctx, m, pb);
         double err = fabs(l + r - whole);
         double loc = tol * (pb - pa) / (b - a);
-        if (err <= loc || err <= rel * fabs(l + r) || sp >= MAX_DEPTH || splits >= MAX_SPLITS ||
-            !(m > pa && m < pb)) {
+        const int ok = err <= loc || err <= rel * fabs(l + r);
+        if (ok || sp >= MAX_DEPTH || splits >= MAX_SPLITS || !(m > pa && m < pb)) {
+            if (!ok) {
+                ++tl_unconverged;
+                tl_errbound += err * tl_mult;
+            }
             total += l + r;
         } else {
             ++splits;
@@ -143,11 +183,17 @@ static int cmp_dbl(const void *x, const void *y)
     return (a > b) - (a < b);
 }
 
+#ifndef MAX_BREAKS
 #define MAX_BREAKS 1024
+#endif
 #define UNIFORM_2D 64   /* initial uniform panels, 2D angle integral */
 #define UNIFORM_3D 2    /* initial uniform panels, each 3D level */
+#ifndef REL_2D
 #define REL_2D 1e-12    /* relative acceptance floor of a panel, 2D */
+#endif
+#ifndef REL_3D
 #define REL_3D 1e-10    /* relative acceptance floor of a panel, 3D */
+#endif
 static double graded(fn1 f, void *ctx, double a, double b, const double *centres,
                      const double *h0, int nc, double tol, int uniform, double rel)
 {
@@ -389,8 +435,13 @@ int oracle_gwn2d(int64_t n, const int32_t *degree, const int64_t *cp_offset, con
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-#pragma omp parallel for schedule(dynamic, 64)
+    long long unconv = 0;
+    double worst = 0.0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : unconv) reduction(max : worst)
     for (int64_t k = 0; k < n_q; ++k) {
+        tl_unconverged = 0;
+        tl_errbound = 0.0;
+        tl_mult = 1.0;
         double s = 0.0;
         curve2 c;
         c.qx = q[2 * k];
@@ -406,7 +457,11 @@ int oracle_gwn2d(int64_t n, const int32_t *degree, const int64_t *cp_offset, con
             s += gwn_curve(&c, eps_on);
         }
         out[k] = s / (2.0 * PI_);
+        unconv += tl_unconverged;
+        worst = fmax(worst, tl_errbound / (2.0 * PI_));
     }
+    g_last_unconverged = unconv;
+    g_last_errbound = worst;
     return 0;
 }
 
@@ -574,7 +629,11 @@ static double outer_f(double t, void *ctx)
     trim_eval(g, t, &u, &v, &du, &dv);
     if (dv == 0.0) return 0.0;
     green_ctx local = *g;
-    return F_inner(&local, u, v) * dv;
+    const double saved = tl_mult;
+    tl_mult = saved * fabs(dv);
+    const double F = F_inner(&local, u, v);
+    tl_mult = saved;
+    return F * dv;
 }
 
 /* Contribution of one trim curve: graded toward the parameters where the
@@ -686,37 +745,17 @@ static double gwn_patch(const patch3 *p, int n_trim, const int32_t *tdeg, const 
         double n[3] = {Su[1] * Sv[2] - Su[2] * Sv[1], Su[2] * Sv[0] - Su[0] * Sv[2], Su[0] * Sv[1] - Su[1] * Sv[0]};
         double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
         if (sqrt(dx * dx + dy * dy + dz * dz) < eps_on && nn > 0.0) {
-            /* inside the visible region only: q on the trimmed-away part is not
-             * on this surface; the interior test uses the trim loops' winding */
-            int visible = 1;
-            if (n_trim > 0) {
-                double wsum = 0.0;
-                for (int cc = 0; cc < n_trim; ++cc) {
-                    /* angle subtended at (u*, v*) by the trim polygon of each curve,
-                     * sampled finely: a crude but sufficient inside test */
-                    int nd = tdeg[cc];
-                    double U[3], V[3], Wt[3];
-                    for (int j = 0; j <= nd; ++j) {
-                        int64_t o = tcoff[cc] + j;
-                        Wt[j] = tw[o]; U[j] = tuv[2 * o] * tw[o]; V[j] = tuv[2 * o + 1] * tw[o];
-                    }
-                    double pu = 0, pv = 0;
-                    for (int s = 0; s <= 64; ++s) {
-                        double B[3], t = s / 64.0;
-                        bernstein(nd, t, B, NULL);
-                        double hu = 0, hv = 0, hw = 0;
-                        for (int j = 0; j <= nd; ++j) { hu += B[j] * U[j]; hv += B[j] * V[j]; hw += B[j] * Wt[j]; }
-                        double cu = hu / hw - g.us, cv = hv / hw - g.vs;
-                        if (s > 0) wsum += atan2(pu * cv - pv * cu, pu * cu + pv * cv);
-                        pu = cu; pv = cv;
-                    }
-                }
-                visible = fabs(wsum) > PI_;
-            }
-            if (visible) {
-                for (int k = 0; k < 3; ++k) n[k] /= nn;
-                return gwn_patch_onsurface(p, n, n_trim, tdeg, tcoff, tuv, tw, eps_on);
-            }
+            /* q on the surface S (within eps_on), taken over the whole
+             * parameter square.  Where the foot point is on the visible
+             * part, the value is the direct one, the mean of the two
+             * one-sided limits.  Where it is on a trimmed-away part, the
+             * patch's value is continuous across S there, so the same mean
+             * is its value.  Either way the mean over q +- delta n is taken,
+             * which also keeps the Green line integrals (whose segments
+             * [0, u] x {v} may pass through the foot point) off the
+             * singularity. */
+            for (int k = 0; k < 3; ++k) n[k] /= nn;
+            return gwn_patch_onsurface(p, n, n_trim, tdeg, tcoff, tuv, tw, eps_on);
         }
     }
     double total = 0.0;
@@ -795,8 +834,13 @@ int oracle_gwn3d(int64_t n, const double *cp_xyz, const double *cp_w, const int6
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-#pragma omp parallel for schedule(dynamic, 1)
+    long long unconv = 0;
+    double worst = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : unconv) reduction(max : worst)
     for (int64_t k = 0; k < n_q; ++k) {
+        tl_unconverged = 0;
+        tl_errbound = 0.0;
+        tl_mult = 1.0;
         patch3 p;
         p.q[0] = q[3 * k]; p.q[1] = q[3 * k + 1]; p.q[2] = q[3 * k + 2];
         double s = 0.0;
@@ -815,8 +859,26 @@ int oracle_gwn3d(int64_t n, const double *cp_xyz, const double *cp_w, const int6
                            trim_cp_w, eps_on);
         }
         out[k] = s / (4.0 * PI_);
+        unconv += tl_unconverged;
+        worst = fmax(worst, tl_errbound / (4.0 * PI_));
     }
+    g_last_unconverged = unconv;
+    g_last_errbound = worst;
     return 0;
+}
+
+/* Number of quadrature panels of the last oracle_gwn2d / oracle_gwn3d call
+ * (on any thread) that were accepted unconverged at a work limit. */
+long long oracle_last_unconverged(void)
+{
+    return g_last_unconverged;
+}
+
+/* Largest per-query error bound (units of w) of those panels in that call:
+ * 0 when every panel met its tolerance. */
+double oracle_last_errbound(void)
+{
+    return g_last_errbound;
 }
 
 /* Number of OpenMP threads a parallel region would use. */

@@ -232,3 +232,71 @@ def test_open_trim_loop_rejected(oracle):
     P = patches((cp, w, W.square_trim()[:3]))
     with pytest.raises(ValueError):
         oracle.gwn3d(P, np.zeros((1, 3)))
+
+
+def test_on_surface_of_trimmed_patch_complementary_trims(oracle, sphere):
+    """On-surface branch for trimmed patches.  One patch of the exact sphere
+    is replaced by two copies with complementary trims: copy A keeps the
+    square with a CW circular hole, copy B has the matching CCW disk as its
+    only loop.  The two visible regions tile the original patch, so the
+    surface stays closed: w = 0.5 exactly on the surface both where A is
+    visible and in A's hole (where B is), and 1 / 0 just inside / outside.
+    A query on the surface lies on the visible part of exactly one copy and
+    on the trimmed-away part of the other, which exercises the oracle's
+    visibility test in both directions."""
+    i, c, r = 230, np.array([0.45, 0.55]), 0.25
+    lst = sphere.to_list()
+    cp, w, _ = lst[i]
+    lst[i] = (cp, w, W.square_trim() + W.circle_trim(c, r, ccw=False))
+    lst.append((cp, w, W.circle_trim(c, r, ccw=True)))
+    P = W.Patches3D.from_list(lst)
+    rng = W.Rng(36, "comp")
+    # (u, v) inside the disk (hole of A) and outside it (visible part of A),
+    # at least 0.05 from the trim circle
+    ang = rng.uniform(6, 0, 2 * math.pi)
+    rad_in = rng.uniform(6, 0.0, r - 0.05)
+    uv_in = c + rad_in[:, None] * np.stack([np.cos(ang), np.sin(ang)], 1)
+    uv_out = rng.uniform((12, 2), 0.05, 0.95)
+    uv_out = uv_out[np.linalg.norm(uv_out - c, axis=1) > r + 0.05][:6]
+    assert uv_out.shape[0] == 6
+    uv = np.concatenate([uv_in, uv_out])
+    S, n, _ = W.eval_patch(cp, w, uv[:, 0], uv[:, 1])
+    got = oracle.gwn3d(P, S)
+    assert np.abs(got - 0.5).max() < 1e-7, got
+    for d in (1e-2, 1e-5):
+        wi = oracle.gwn3d(P, S - d * n)
+        wo = oracle.gwn3d(P, S + d * n)
+        assert np.abs(wi - 1).max() < 1e-9 and np.abs(wo).max() < 1e-9, d
+    assert oracle.last_errbound <= oracle.STRICT_ERRBOUND
+
+
+def test_unconverged_quadrature_is_reported(oracle, sphere, tmp_path):
+    """Non-convergence is reported, not silent.  The oracle rebuilt with a
+    split budget of 0 per adaptive call (every panel is accepted as first
+    estimated) and no room for graded breakpoints (only the two uniform
+    panels per level) cannot resolve the density's peak 1e-4 from the
+    sphere: the count and the error bound must show it.  The same query with the normal budget converges (count 0 or a bound
+    far below the strict threshold)."""
+    import ctypes
+    import subprocess
+    lib = tmp_path / "oracle_small_budget.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-DMAX_SPLITS=0", "-DMAX_BREAKS=3", "-o",
+                           str(lib), oracle.SRC, "-lm"])
+    L = ctypes.CDLL(str(lib))
+    L.oracle_gwn3d.argtypes = oracle.lib().oracle_gwn3d.argtypes
+    L.oracle_last_unconverged.restype = ctypes.c_longlong
+    L.oracle_last_errbound.restype = ctypes.c_double
+    S, n, _ = W.eval_patch(sphere.cp_xyz[100], sphere.cp_w[100], 0.37, 0.61)
+    q = np.ascontiguousarray((S - 1e-4 * n)[None])
+    arrs = [np.ascontiguousarray(a, dtype=t) for a, t in
+            [(sphere.cp_xyz, np.float64), (sphere.cp_w, np.float64), (sphere.trim_offset, np.int64),
+             (sphere.trim_degree, np.int32), (sphere.trim_cp_offset, np.int64), (sphere.trim_cp_uv, np.float64),
+             (sphere.trim_cp_w, np.float64)]]
+    out = np.empty(1)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert L.oracle_gwn3d(sphere.n, *[ptr(a) for a in arrs], 1, ptr(q), ptr(out),
+                          oracle.default_eps_on(*sphere.bbox()), 1) == 0
+    assert L.oracle_last_unconverged() > 0 and L.oracle_last_errbound() > oracle.STRICT_ERRBOUND, \
+        (L.oracle_last_unconverged(), L.oracle_last_errbound())
+    w = oracle.gwn3d(sphere, q)
+    assert oracle.last_errbound <= oracle.STRICT_ERRBOUND and abs(w[0] - 1.0) < 1e-9
