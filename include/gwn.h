@@ -219,14 +219,22 @@ gwn_status gwn_get_params(gwn_handle h, gwn_params *out);
  * (x, y[, z]); out_gwn: device double[n]; out_inside: device uint8[n]
  * (1 when w >= 0.5) or NULL.  n may be 0.  Asynchronous on `stream`.
  * Errors: GWN_EINVAL (NULL handle, n < 0, NULL buffers with n > 0, host-only
- * handle), GWN_EHIP, GWN_EOVERFLOW (reported by the NEXT call on the handle
- * after a kernel hit a stack limit; the affected outputs are NaN).
+ * handle), GWN_EHIP, GWN_EOVERFLOW (a query of an earlier call on the handle
+ * hit a traversal, near-field or bisection limit; its output is NaN.  Each
+ * such call is reported once, by the first call on the handle that starts
+ * after the earlier call's work has completed on its stream).
  * Scratch comes from the device's default stream-ordered pool (hipMallocAsync
  * on `stream`, freed on it at the end of the call); building a model for a
  * device raises that pool's release threshold to 1 GiB, process-wide, so the
  * scratch stays mapped between calls. */
 gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
                      uint8_t *out_inside, void *stream);
+
+/* Device scratch bytes one gwn_query / gwn_query_batch call takes at once for
+ * n query rows in n_seg segments (exact for n_seg = 1, an upper bound
+ * otherwise), for admission by memory budget.  Host-only; needs a HIP
+ * runtime (the sort's temporary size is asked from it). */
+gwn_status gwn_query_scratch_bytes(gwn_handle h, int64_t n, int32_t n_seg, int64_t *bytes);
 
 /* Batched query over several models in shared launches (the served form).
  * Segment s covers query rows [seg_offset[s], seg_offset[s+1]) of `points`,
@@ -260,10 +268,9 @@ gwn_status gwn_query_counters(gwn_handle h, const double *points, int64_t n, int
                               void *stream);
 
 /* Memory accounting: bytes resident on the device for this model, and device
- * scratch bytes needed per query by gwn_query / gwn_query_batch.  A launch
- * of fewer than 2^18 queries spreads them over up to 4096 waves; in 3D that
- * takes at most 4096 x 64 per-query slots of the near-field pass (about
- * 72 MB) in place of the per-query figure. */
+ * scratch bytes per query of a gwn_query / gwn_query_batch launch, without
+ * the sort's temporary storage and alignment padding (gwn_query_scratch_bytes
+ * gives the exact bytes of a launch). */
 gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_scratch);
 
 /* Host-side inspection of a built model (also for host-only handles).  Copies

@@ -426,11 +426,19 @@ extern "C" gwn_status gwn_get_params(gwn_handle h, gwn_params *out)
 
 static gwn_status check_flag(Model &m)
 {
-    // Lazily read the overflow flag copied back by the previous call.
-    if (!m.flag_event) return GWN_OK;
-    if (hipEventQuery((hipEvent_t)m.flag_event) == hipSuccess && m.h_flag && *m.h_flag) {
-        *m.h_flag = 0;
-        return fail(GWN_EOVERFLOW, "a previous query hit a traversal/near-field stack limit (outputs set to NaN)");
+    // The device keeps a monotonic count of the queries that hit a limit;
+    // each launch copies it back.  Once the latest copy has landed, a count
+    // above the one already reported is reported once.  The count is never
+    // reset, so a copy that lands later can only carry a larger value and
+    // no overflow is lost or reported twice.
+    if (!m.flag_event || !m.h_flag) return GWN_OK;
+    if (hipEventQuery((hipEvent_t)m.flag_event) != hipSuccess) return GWN_OK;
+    const uint32_t now = (uint32_t)*m.h_flag;
+    if (now != m.flag_seen) {
+        const uint32_t fresh = now - m.flag_seen;
+        m.flag_seen = now;
+        return fail(GWN_EOVERFLOW, std::to_string(fresh) + " query(ies) of an earlier call hit a traversal or "
+                                   "near-field limit (their outputs are NaN)");
     }
     return GWN_OK;
 }
@@ -444,8 +452,8 @@ static gwn_status after_launch(Model &m, void *stream)
     return GWN_OK;
 }
 
-extern "C" gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
-                                uint8_t *out_inside, void *stream)
+static gwn_status query_common(gwn_handle h, const double *points, int64_t n, double *out_gwn,
+                               uint8_t *out_inside, void *stream)
 {
     if (!h) return fail(GWN_EINVAL, "NULL handle");
     if (n < 0) return fail(GWN_EINVAL, "n < 0");
@@ -457,11 +465,27 @@ extern "C" gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, d
     if (n == 0) return GWN_OK;
     hipError_t e = hipSetDevice(h->m.device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    std::vector<Segment> segs{{&h->m, 0, n}};
     std::string err;
-    s = launch_queries(segs, h->m.dim, points, out_gwn, out_inside, nullptr, stream, err);
+    ExtScratch ext;
+    std::vector<Segment> segs{{&h->m, 0, n}};
+    s = launch_queries(segs, h->m.dim, points, out_gwn, out_inside, nullptr, stream, err, ext);
     if (s) return fail(s, err);
     return after_launch(h->m, stream);
+}
+
+extern "C" gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
+                                uint8_t *out_inside, void *stream)
+{
+    return query_common(h, points, n, out_gwn, out_inside, stream);
+}
+
+extern "C" gwn_status gwn_query_scratch_bytes(gwn_handle h, int64_t n, int32_t n_seg, int64_t *bytes)
+{
+    if (!h || !bytes) return fail(GWN_EINVAL, "NULL handle or output");
+    if (n < 0 || n_seg < 0) return fail(GWN_EINVAL, "n and n_seg must be >= 0");
+    std::string err;
+    gwn_status s = query_scratch_bytes(h->m.dim, n, n_seg, *bytes, err);
+    return s ? fail(s, err) : GWN_OK;
 }
 
 extern "C" gwn_status gwn_query_counters(gwn_handle h, const double *points, int64_t n, int64_t *counters,
@@ -530,8 +554,10 @@ extern "C" gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *
     if (!h) return fail(GWN_EINVAL, "NULL handle");
     if (resident) *resident = h->m.arena_bytes + 256;
     // keys x2, permutation x2, sort temp; 3D adds the near-field pass:
-    // partial sum, count, 64 leaf slots, flag (per query, rounded up)
-    if (per_query) *per_query = 8 + 8 + 4 + 4 + 16 + (h->m.dim == 3 ? 8 + 4 + 4 * 64 + 4 : 0);
+    // partial sum, count, 64 leaf slots, reclassify flag.  Per query at 64
+    // queries per wave; launches under 2^18 queries take more per query
+    // (gwn_query_scratch_bytes gives the exact figure of a launch).
+    if (per_query) *per_query = 8 + 8 + 4 + 4 + 16 + (h->m.dim == 3 ? 8 + 4 + 4 * 64 + 1 : 0);
     return GWN_OK;
 }
 

@@ -150,7 +150,7 @@ struct DevModel {
     const void *qnodes;     // QNode3* (3D)
     const void *mpole;      // 3D: per node 72 doubles, 1/r then scaled multipole moments
     const void *fmpole;     // 3D: FP32 mirror of mpole
-    int32_t *flag;          // overflow flag (device)
+    int32_t *flag;          // overflow count (device): queries that hit a limit, never reset
     int32_t dim;
     int32_t n_nodes;
     int32_t order;
@@ -234,8 +234,9 @@ struct Model {
     int device = -1;
     void *d_arena = nullptr;
     int64_t arena_bytes = 0;
-    int32_t *d_flag = nullptr;
-    int32_t *h_flag = nullptr;     // pinned
+    int32_t *d_flag = nullptr;     // device overflow count (monotonic)
+    int32_t *h_flag = nullptr;     // pinned copy of it, taken after each launch
+    uint32_t flag_seen = 0;        // count already reported as GWN_EOVERFLOW
     void *flag_event = nullptr;    // hipEvent_t
     DevModel dev{};
 };
@@ -269,8 +270,17 @@ struct Segment {
     const Model *model;
     int64_t q_begin, q_end;   // rows of the points/output arrays
 };
+// Scratch handed to a launch instead of stream-ordered allocation;
+// ptr == nullptr: allocate from the pool.
+struct ExtScratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
 gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const double *points,
                           double *out_gwn, uint8_t *out_inside, int64_t *counters, void *stream,
-                          std::string &err);
+                          std::string &err, const ExtScratch &ext = ExtScratch{});
+// Scratch bytes of one query call over n rows in n_seg segments (an upper
+// bound; exact for one segment).
+gwn_status query_scratch_bytes(int dim, int64_t n, int32_t n_seg, int64_t &bytes, std::string &err);
 
 }  // namespace gwn

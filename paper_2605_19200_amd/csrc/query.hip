@@ -471,7 +471,7 @@ __device__ __forceinline__ void query2d_body(const LaunchTable &T, const double 
     if (valid) {
         if (overflow) {
             wq = NAN;
-            atomicOr(M.flag, 1);
+            atomicAdd((unsigned int *)M.flag, 1u);
             if (COUNT) ctr.v[GWN_C_OVERFLOW]++;
         }
         if (out_w) out_w[row] = wq;
@@ -504,9 +504,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     query2d_body<COUNT, true>(T, pts, perm, out_w, out_in, counters, S);
 }
 
-// 3D kernels live in query3d.hip
+// 3D kernels live in query3d.hip; near_buf holds near.total bytes
 gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t *perm, double *out_w,
-                          uint8_t *out_in, long long *counters, hipStream_t stream, std::string &err);
+                          uint8_t *out_in, long long *counters, char *near_buf, const NearBytes &near,
+                          hipStream_t stream, std::string &err);
 
 // ---------------------------------------------------------------------------
 // host launcher
@@ -560,24 +561,62 @@ static gwn_status hip_err(hipError_t e, const char *what, std::string &err)
     return GWN_EHIP;
 }
 
+// Queries per wave of a launch of n queries: a launch of fewer than 2^18
+// queries spreads them over up to 4096 waves (at least 8 queries each):
+// scattered queries share few nodes, so a wave's cost grows with its number
+// of queries, and more waves keep more of the 1024 SIMDs busy.  Each query's
+// value does not depend on its wave mates, so results are the same at any
+// spread.
+static int32_t queries_per_wave(int64_t n)
+{
+    int32_t qpw = 64;
+    while (qpw > 8 && (int64_t)(qpw / 2) * 4096 >= n) qpw /= 2;
+    return qpw;
+}
+
+// Scratch of one launch chunk, in one buffer with 256-byte aligned parts:
+// sort keys and row indices (double-buffered), the radix sort's temporary
+// storage and, in 3D, the near-field pass's per-slot records.  Nothing in it
+// needs to start at zero: every record is written before it is read.  A
+// small launch sorts on the top 24 key bits only (segment and the coarse
+// Morton levels, far finer than its waves): fewer radix passes and no effect
+// on any value.
+struct ScratchPlan {
+    size_t keys = 0, vals = 0, temp = 0, temp_bytes = 0;
+    NearBytes near;
+    size_t total = 0;
+    int sort_lo = 0;
+};
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+static hipError_t plan_scratch(int dim, int64_t n, int64_t slots, hipStream_t stream, ScratchPlan &P)
+{
+    P.sort_lo = n < (1 << 16) ? 30 : 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, P.temp_bytes, (uint64_t *)nullptr,
+                                                      (uint64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
+                                                      (int)n, P.sort_lo, 54, stream);
+    if (e != hipSuccess) return e;
+    P.keys = al256(sizeof(uint64_t) * n);
+    P.vals = al256(sizeof(int32_t) * n);
+    P.temp = al256(P.temp_bytes);
+    P.near = dim == 3 ? near_scratch_bytes(slots) : NearBytes{};
+    P.total = 2 * P.keys + 2 * P.vals + P.temp + P.near.total;
+    return hipSuccess;
+}
+
 static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size_t s1, int dim,
                                const double *points, double *out_gwn, uint8_t *out_inside, int64_t *counters,
-                               hipStream_t stream, std::string &err)
+                               hipStream_t stream, const ExtScratch &ext, std::string &err)
 {
     LaunchTable T;
     std::memset(&T, 0, sizeof T);
     std::vector<const Model *> models;
     T.n_seg = (int32_t)(s1 - s0);
     const int64_t row0 = segs[s0].q_begin;
-    // A launch of fewer than 2^18 queries spreads them over up to 4096
-    // waves (at least 8 queries each): scattered queries share few nodes, so
-    // a wave's cost grows with its number of queries, and more waves keep
-    // more of the 1024 SIMDs busy.  Each query's value does not depend on
-    // its wave mates, so results are the same at any spread.
     int64_t n_all = 0;
     for (size_t k = s0; k < s1; ++k) n_all += segs[k].q_end - segs[k].q_begin;
-    int32_t qpw = 64;
-    while (qpw > 8 && (int64_t)(qpw / 2) * 4096 >= n_all) qpw /= 2;
+    const int32_t qpw = queries_per_wave(n_all);
     T.qpw = qpw;
     int64_t q = 0;
     int32_t wv = 0;
@@ -608,32 +647,32 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     double *ow = out_gwn ? out_gwn + row0 : nullptr;
     uint8_t *oi = out_inside ? out_inside + row0 : nullptr;
 
-    // scratch: keys[2n] (u64), vals[2n] (i32), sort temp.  A small launch
-    // sorts on the top 24 key bits only (segment and the coarse Morton
-    // levels, far finer than its waves): fewer radix passes, fewer kernel
-    // launches, and no effect on any value.
-    const int sort_lo = n < (1 << 16) ? 30 : 0;
-    size_t temp_bytes = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                                      (int32_t *)nullptr, (int32_t *)nullptr, (int)n, sort_lo, 54,
-                                                      stream);
+    ScratchPlan P;
+    hipError_t e = plan_scratch(dim, n, (int64_t)T.n_waves * T.qpw, stream, P);
     if (e != hipSuccess) return hip_err(e, "radix sort sizing", err);
-    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t b_keys = al(sizeof(uint64_t) * n), b_vals = al(sizeof(int32_t) * n);
-    const size_t total = 2 * b_keys + 2 * b_vals + al(temp_bytes);
-    char *scratch = nullptr;
-    e = hipMallocAsync((void **)&scratch, total, stream);
-    if (e != hipSuccess) return hip_err(e, "hipMallocAsync scratch", err);
-    uint64_t *k_in = (uint64_t *)scratch, *k_out = (uint64_t *)(scratch + b_keys);
-    int32_t *v_in = (int32_t *)(scratch + 2 * b_keys), *v_out = (int32_t *)(scratch + 2 * b_keys + b_vals);
-    void *temp = scratch + 2 * b_keys + 2 * b_vals;
+    char *buf = nullptr;
+    if (ext.ptr) {
+        if (P.total > ext.bytes) {
+            err = "launch needs " + std::to_string(P.total) + " bytes of scratch, above the fixed " +
+                  std::to_string(ext.bytes);
+            return GWN_EINVAL;
+        }
+        buf = (char *)ext.ptr;
+    } else {
+        e = hipMallocAsync((void **)&buf, P.total, stream);
+        if (e != hipSuccess) return hip_err(e, "hipMallocAsync scratch", err);
+    }
+    uint64_t *k_in = (uint64_t *)buf, *k_out = (uint64_t *)(buf + P.keys);
+    int32_t *v_in = (int32_t *)(buf + 2 * P.keys), *v_out = (int32_t *)(buf + 2 * P.keys + P.vals);
+    void *temp = buf + 2 * P.keys + 2 * P.vals;
+    char *near_buf = buf + 2 * P.keys + 2 * P.vals + P.temp;
 
     const int grid_q = (int)((n + kBlock - 1) / kBlock);
     gwn_status st = GWN_OK;
     hipLaunchKernelGGL(k_keys, dim3(grid_q), dim3(kBlock), 0, stream, T, dim, pts, k_in, v_in, n);
     e = hipGetLastError();
     if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, k_in, k_out, v_in, v_out, (int)n, sort_lo, 54,
+        e = hipcub::DeviceRadixSort::SortPairs(temp, P.temp_bytes, k_in, k_out, v_in, v_out, (int)n, P.sort_lo, 54,
                                                stream);
     if (e != hipSuccess) st = hip_err(e, "key/sort launch", err);
     if (!st) {
@@ -662,17 +701,20 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
             e = hipGetLastError();
             if (e != hipSuccess) st = hip_err(e, "query launch", err);
         } else {
-            st = launch_query3d(T, pts, v_out, ow, oi, (long long *)counters, stream, err);
+            st = launch_query3d(T, pts, v_out, ow, oi, (long long *)counters, near_buf, P.near, stream, err);
         }
         prof_end(stream, ev0);
     }
-    hipError_t e2 = hipFreeAsync(scratch, stream);
-    if (!st && e2 != hipSuccess) st = hip_err(e2, "hipFreeAsync scratch", err);
+    if (!ext.ptr) {
+        hipError_t e2 = hipFreeAsync(buf, stream);
+        if (!st && e2 != hipSuccess) st = hip_err(e2, "hipFreeAsync scratch", err);
+    }
     return st;
 }
 
 gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const double *points, double *out_gwn,
-                          uint8_t *out_inside, int64_t *counters, void *stream, std::string &err)
+                          uint8_t *out_inside, int64_t *counters, void *stream, std::string &err,
+                          const ExtScratch &ext)
 {
     hipStream_t s = (hipStream_t)stream;
     size_t a = 0;
@@ -688,10 +730,27 @@ gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const doubl
             if (b > a && segs[b].q_begin != segs[b - 1].q_end) break;
             ++b;
         }
-        gwn_status st = launch_chunk(segs, a, b, dim, points, out_gwn, out_inside, counters, s, err);
+        gwn_status st = launch_chunk(segs, a, b, dim, points, out_gwn, out_inside, counters, s, ext, err);
         if (st) return st;
         a = b;
     }
+    return GWN_OK;
+}
+
+gwn_status query_scratch_bytes(int dim, int64_t n, int32_t n_seg, int64_t &bytes, std::string &err)
+{
+    bytes = 0;
+    if (n <= 0) return GWN_OK;
+    // the launch is cut into chunks of at most kMaxSeg segments, one after
+    // another on the stream: the largest chunk's scratch bounds the call's.
+    // Each segment after the first adds at most one partly filled wave.
+    const int32_t segs_per_chunk = std::min<int32_t>(std::max<int32_t>(n_seg, 1), kMaxSeg);
+    const int32_t qpw = queries_per_wave(n);
+    const int64_t waves = (n + qpw - 1) / qpw + (segs_per_chunk - 1);
+    ScratchPlan P;
+    hipError_t e = plan_scratch(dim, n, waves * qpw, nullptr, P);
+    if (e != hipSuccess) return hip_err(e, "radix sort sizing", err);
+    bytes = (int64_t)P.total;
     return GWN_OK;
 }
 

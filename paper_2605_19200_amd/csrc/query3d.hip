@@ -42,20 +42,16 @@ __constant__ QuadTables c_quad;
 
 __device__ __forceinline__ void ctr_add(Ctr &c, int k, long long v) { c.v[k] += v; }
 
-// Near-field leaves recorded per query by the traversal, in its DFS order
-// (at most kNearSlots; more sets the overflow flag and gives NaN).
-constexpr int kNearSlots = 64;
-
 // Runs of 16 blocks per XCD (see xcd_block); both 3D passes must map
 // blocks to waves the same way, since the near-field pass reads the
 // traversal's per-slot scratch.
 constexpr int kXcdRun3 = 16;
 
 struct NearScratch {
-    double *part;      // [n_waves * 64] solid angle of the far field and node-set leaves
-    int32_t *cnt;      // [n_waves * 64] near leaves met by the traversal
-    int32_t *list;     // [n_waves * 64 * kNearSlots] their node indices
-    uint8_t *need;     // [n_waves * 64] mixed form: lane re-evaluated in FP64
+    double *part;      // [n_waves * qpw] solid angle of the far field and node-set leaves
+    int32_t *cnt;      // [n_waves * qpw] near leaves met by the traversal
+    int32_t *list;     // [n_waves * qpw * kNearSlots] their node indices
+    uint8_t *need;     // [n_waves * qpw] mixed form: query re-evaluated in FP64
 };
 
 // Direct solid angle of one leaf at q by its precomputed node set, chosen by
@@ -292,8 +288,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
     const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + lane;
-    const int64_t slot = (int64_t)wave * 64 + lane;
+    // per-query records are indexed by the query's position in the wave
+    // grid (qpw per wave), read and written by valid lanes only
     const bool valid = lane < T.qpw && pos < T.qoff[s + 1];
+    const int64_t slot = (int64_t)wave * T.qpw + (valid ? lane : 0);
     const bool act = valid && (!RECLASS || NS.need[slot]);
     const uint64_t mask = __ballot(act);
     if (!mask) return;
@@ -341,8 +339,10 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
     const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + lane;
-    const int64_t slot = (int64_t)wave * 64 + lane;
+    // per-query records are indexed by the query's position in the wave
+    // grid (qpw per wave), read and written by valid lanes only
     const bool valid = lane < T.qpw && pos < T.qoff[s + 1];
+    const int64_t slot = (int64_t)wave * T.qpw + (valid ? lane : 0);
     const bool act = valid && (!RECLASS || NS.need[slot]);
     if (!__ballot(act)) return;
     const int row = act ? perm[pos] : 0;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
         const double ox = __shfl(qx, owner), oy = __shfl(qy, owner), oz = __shfl(qz, owner);
         double v = 0.0;
         if (has) {
-            const int node = NS.list[((int64_t)wave * 64 + owner) * kNearSlots + (t - oexcl)];
+            const int node = NS.list[((int64_t)wave * T.qpw + owner) * kNearSlots + (t - oexcl)];
             const Node3 *nd = (const Node3 *)M.nodes + node;
             const int leaf = -1 - nd->right;
             v = near3d<COUNT>(c_quad, (const Prim3 *)M.prims + leaf, (const Trim3 *)M.trims, ox, oy, oz, M.eps_on,
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
         double wq = (NS.part[slot] + near_sum) * (1.0 / (4.0 * kPi));
         if (overflow) {
             wq = NAN;
-            atomicOr(M.flag, 1);
+            atomicAdd((unsigned int *)M.flag, 1u);
             if (COUNT) ctr.v[GWN_C_OVERFLOW]++;
         }
         const bool band = !RECLASS && M.precision == GWN_MIXED && !overflow && fabs(wq - 0.5) < M.band;
@@ -428,7 +428,8 @@ static hipError_t ensure_tables()
 }
 
 gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t *perm, double *out_w,
-                          uint8_t *out_in, long long *counters, hipStream_t stream, std::string &err)
+                          uint8_t *out_in, long long *counters, char *near_buf, const NearBytes &near,
+                          hipStream_t stream, std::string &err)
 {
     hipError_t e = ensure_tables();
     if (e != hipSuccess) {
@@ -437,22 +438,12 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
     }
     const int grid = (T.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
     if (grid == 0) return GWN_OK;
-    // per-slot scratch of the two passes (stream ordered)
-    const size_t ns = (size_t)T.n_waves * 64;
-    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t b_part = al(ns * sizeof(double)), b_cnt = al(ns * sizeof(int32_t)),
-                 b_list = al(ns * kNearSlots * sizeof(int32_t)), b_need = al(ns);
-    char *buf = nullptr;
-    e = hipMallocAsync((void **)&buf, b_part + b_cnt + b_list + b_need, stream);
-    if (e != hipSuccess) {
-        err = std::string("hipMallocAsync near-field scratch: ") + hipGetErrorString(e);
-        return GWN_ENOMEM;
-    }
+    // per-slot records of the two passes, carved from the launch's scratch
     NearScratch NS;
-    NS.part = (double *)buf;
-    NS.cnt = (int32_t *)(buf + b_part);
-    NS.list = (int32_t *)(buf + b_part + b_cnt);
-    NS.need = (uint8_t *)(buf + b_part + b_cnt + b_list);
+    NS.part = (double *)near_buf;
+    NS.cnt = (int32_t *)(near_buf + near.part);
+    NS.list = (int32_t *)(near_buf + near.part + near.cnt);
+    NS.need = (uint8_t *)(near_buf + near.part + near.cnt + near.list);
     bool any_mixed = false;
     for (int j = 0; j < T.n_seg; ++j) any_mixed |= T.models[T.seg_model[j]].precision == GWN_MIXED;
     const dim3 g(grid), b(kBlock);
@@ -474,13 +465,8 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
         }
     }
     e = hipGetLastError();
-    const hipError_t e2 = hipFreeAsync(buf, stream);
     if (e != hipSuccess) {
         err = std::string("3D query launch: ") + hipGetErrorString(e);
-        return GWN_EHIP;
-    }
-    if (e2 != hipSuccess) {
-        err = std::string("hipFreeAsync near-field scratch: ") + hipGetErrorString(e2);
         return GWN_EHIP;
     }
     return GWN_OK;

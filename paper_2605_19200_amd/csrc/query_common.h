@@ -27,6 +27,31 @@ struct Ctr {
     long long v[GWN_NCOUNTERS];
 };
 
+// Near-field leaves recorded per query by the 3D traversal (at most
+// kNearSlots; more sets the overflow count and gives NaN).
+constexpr int kNearSlots = 64;
+
+// Byte sizes of the 3D near-field pass's per-query records (one slot per
+// query position of the wave grid, n_waves x queries per wave), each part
+// 256-byte aligned: the far-field and node-set sum, the near-leaf count,
+// kNearSlots leaf indices, the reclassify flag.
+struct NearBytes {
+    size_t part = 0, cnt = 0, list = 0, need = 0, total = 0;
+};
+
+inline NearBytes near_scratch_bytes(int64_t slots)
+{
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t ns = (size_t)slots;
+    NearBytes b;
+    b.part = al(ns * sizeof(double));
+    b.cnt = al(ns * sizeof(int32_t));
+    b.list = al(ns * kNearSlots * sizeof(int32_t));
+    b.need = al(ns);
+    b.total = b.part + b.cnt + b.list + b.need;
+    return b;
+}
+
 __device__ __forceinline__ int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 {

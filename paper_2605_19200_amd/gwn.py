@@ -24,7 +24,7 @@ GWN_NCOUNTERS = len(COUNTER_NAMES)
  GWN_I_FARBETA) = range(8)
 
 EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
-            "gwn_get_params", "gwn_query",
+            "gwn_get_params", "gwn_query", "gwn_query_scratch_bytes",
             "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
             "gwn_free", "gwn_last_error"]
 
@@ -81,6 +81,7 @@ def lib():
             ("gwn_set_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_get_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_query", [vp, vp, i64, vp, vp, vp]),
+            ("gwn_query_scratch_bytes", [vp, i64, i32, ctypes.POINTER(i64)]),
             ("gwn_query_batch", [i32, vp, vp, vp, vp, vp, vp]),
             ("gwn_query_counters", [vp, vp, i64, vp, vp]),
             ("gwn_model_bytes", [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
@@ -118,6 +119,35 @@ def gwn_default_params(**overrides) -> gwn_params:
     return p
 
 
+# dimension and device of every handle built here, for argument checks
+_handles: dict = {}
+
+
+def _handle_key(h):
+    return h.value if isinstance(h, ctypes.c_void_p) else int(h)
+
+
+def _handle_info(h):
+    """(dim, device) of a handle."""
+    if h is None or _handle_key(h) in (None, 0):
+        raise ValueError("NULL handle")
+    info = _handles.get(_handle_key(h))
+    if info is None:
+        p = gwn_params()
+        _check(lib().gwn_get_params(h, ctypes.byref(p)))
+        summ = np.empty(8)
+        cnt = ctypes.c_int64()
+        _check(lib().gwn_inspect(h, GWN_I_SUMMARY, _p(summ), 1, ctypes.byref(cnt)))
+        info = (int(summ[0]), int(p.device))
+        _handles[_handle_key(h)] = info
+    return info
+
+
+def _register(h, dim, params):
+    dev = params.device if params is not None else 0
+    _handles[_handle_key(h)] = (dim, int(dev))
+
+
 def gwn_build2d(curves, params: gwn_params | None = None):
     """Build a 2D model from a ``workloads.Curves2D``; returns the handle."""
     deg, off = _np(curves.degree, np.int32), _np(curves.cp_offset, np.int64)
@@ -125,6 +155,7 @@ def gwn_build2d(curves, params: gwn_params | None = None):
     c = gwn_curves2d(curves.n, _p(deg), _p(off), _p(xy), _p(w))
     h = ctypes.c_void_p()
     _check(lib().gwn_build2d(ctypes.byref(c), ctypes.byref(params) if params else None, ctypes.byref(h)))
+    _register(h, 2, params)
     return h
 
 
@@ -136,6 +167,7 @@ def gwn_build3d(patches, params: gwn_params | None = None):
     c = gwn_patches3d(patches.n, *[_p(a) for a in arrs])
     h = ctypes.c_void_p()
     _check(lib().gwn_build3d(ctypes.byref(c), ctypes.byref(params) if params else None, ctypes.byref(h)))
+    _register(h, 3, params)
     return h
 
 
@@ -176,21 +208,91 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+def _check_layout(name, t, dtype, shape):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _check_device(name, t, device):
+    import torch
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU, got {t.device}")
+    if device < 0:
+        raise ValueError("host-only handle cannot be queried")
+    idx = t.device.index if t.device.index is not None else torch.cuda.current_device()
+    if idx != device:
+        raise ValueError(f"{name} is on cuda:{idx}, the model on cuda:{device}")
+
+
+def _check_tensors(device, specs):
+    """The kernels read and write raw device pointers: refuse anything but
+    contiguous tensors of the expected dtype and shape on the model's device
+    (ValueError before any launch).  specs: (name, tensor, dtype, shape)."""
+    for name, t, dt, shape in specs:
+        _check_layout(name, t, dt, shape)
+    for name, t, _, _ in specs:
+        _check_device(name, t, device)
+
+
+def _check_query_args(dim, device, points, out_gwn, out_inside, n=None):
+    import torch
+    if not isinstance(points, torch.Tensor) or points.ndim != 2:
+        raise ValueError(f"points must be a [n, {dim}] tensor")
+    n = points.shape[0] if n is None else n
+    specs = [("points", points, torch.float64, (n, dim)), ("out_gwn", out_gwn, torch.float64, (n,))]
+    if out_inside is not None:
+        specs.append(("out_inside", out_inside, torch.uint8, (n,)))
+    _check_tensors(device, specs)
+
+
+def _query_call(fn, h, points, out_gwn, out_inside, stream):
+    dim, device = _handle_info(h)
+    _check_query_args(dim, device, points, out_gwn, out_inside)
+    n = points.shape[0]
+    _check(fn(h, ctypes.c_void_p(points.data_ptr()), n, ctypes.c_void_p(out_gwn.data_ptr()),
+              ctypes.c_void_p(out_inside.data_ptr()) if out_inside is not None else None, _stream_ptr(stream)))
+
+
 def gwn_query(h, points, out_gwn, out_inside=None, stream=None):
     """points: device float64 tensor [n, dim]; out_gwn: device float64 [n];
     out_inside: device uint8 [n] or None.  Asynchronous on `stream`."""
-    n = points.shape[0]
-    _check(lib().gwn_query(h, ctypes.c_void_p(points.data_ptr()), n, ctypes.c_void_p(out_gwn.data_ptr()),
-                           ctypes.c_void_p(out_inside.data_ptr()) if out_inside is not None else None,
-                           _stream_ptr(stream)))
+    _query_call(lib().gwn_query, h, points, out_gwn, out_inside, stream)
+
+
+def gwn_query_scratch_bytes(h, n: int, n_seg: int = 1) -> int:
+    """Device scratch bytes of one query call over n rows in n_seg segments."""
+    b = ctypes.c_int64()
+    _check(lib().gwn_query_scratch_bytes(h, int(n), int(n_seg), ctypes.byref(b)))
+    return b.value
 
 
 def gwn_query_batch(models, seg_offset, points, out_gwn, out_inside=None, stream=None):
     """models: list of handles (one per segment); seg_offset: host int64
     [n_seg + 1]; points/out_*: device tensors covering all segments."""
+    import torch
     n_seg = len(models)
-    arr = (ctypes.c_void_p * max(n_seg, 1))(*[m.value if isinstance(m, ctypes.c_void_p) else m for m in models])
     off = _np(seg_offset, np.int64)
+    if off.ndim != 1 or off.size != n_seg + 1:
+        raise ValueError(f"seg_offset must hold n_seg + 1 = {n_seg + 1} entries, got {off.size}")
+    if n_seg:
+        if off[0] != 0 or np.any(np.diff(off) < 0):
+            raise ValueError("seg_offset must start at 0 and be non-decreasing")
+        infos = [_handle_info(m) for m in models]
+        dims, devs = {d for d, _ in infos}, {v for _, v in infos}
+        if len(dims) != 1 or len(devs) != 1:
+            raise ValueError("all models of a batch must share one dimension and one device")
+        (dim,), (device,) = dims, devs
+        if not isinstance(points, torch.Tensor) or points.ndim != 2:
+            raise ValueError(f"points must be a [n, {dim}] tensor")
+        _check_query_args(dim, device, points, out_gwn, out_inside, n=int(off[-1]))
+    arr = (ctypes.c_void_p * max(n_seg, 1))(*[m.value if isinstance(m, ctypes.c_void_p) else m for m in models])
     _check(lib().gwn_query_batch(n_seg, ctypes.cast(arr, ctypes.c_void_p), _p(off),
                                  ctypes.c_void_p(points.data_ptr()), ctypes.c_void_p(out_gwn.data_ptr()),
                                  ctypes.c_void_p(out_inside.data_ptr()) if out_inside is not None else None,
@@ -199,6 +301,12 @@ def gwn_query_batch(models, seg_offset, points, out_gwn, out_inside=None, stream
 
 def gwn_query_counters(h, points, counters, stream=None):
     """counters: device int64 tensor [GWN_NCOUNTERS] (overwritten)."""
+    import torch
+    dim, device = _handle_info(h)
+    if not isinstance(points, torch.Tensor) or points.ndim != 2:
+        raise ValueError(f"points must be a [n, {dim}] tensor")
+    _check_tensors(device, [("points", points, torch.float64, (points.shape[0], dim)),
+                            ("counters", counters, torch.int64, (GWN_NCOUNTERS,))])
     _check(lib().gwn_query_counters(h, ctypes.c_void_p(points.data_ptr()), points.shape[0],
                                     ctypes.c_void_p(counters.data_ptr()), _stream_ptr(stream)))
 
@@ -238,6 +346,7 @@ def gwn_profile(enable: bool):
 
 def gwn_free(h):
     if h is not None:
+        _handles.pop(_handle_key(h), None)
         _check(lib().gwn_free(h))
 
 
@@ -268,6 +377,8 @@ class Model:
 
     def query(self, points, out=None, inside=None, stream=None):
         import torch
+        if not isinstance(points, torch.Tensor) or points.ndim != 2:
+            raise ValueError(f"points must be a [n, {self.dim}] tensor")
         n = points.shape[0]
         if out is None:
             out = torch.empty(n, dtype=torch.float64, device=points.device)

@@ -107,3 +107,56 @@ def test_header_is_plain_c(tmp_path):
                         os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
 
+
+
+def test_query_arguments_checked_before_any_launch():
+    """The binding refuses every malformed tensor before the library is
+    called: wrong dtype, wrong shape or dimension, a strided view, outputs
+    of the wrong length or type, host tensors, short segment tables and
+    mixed 2D / 3D batches (all raise ValueError, no launch)."""
+    import torch
+    curves, _ = W.config1()
+    h = G.gwn_build2d(curves, host_params())
+    n = 10
+    good = torch.zeros((n, 2), dtype=torch.float64)
+    out = torch.zeros(n, dtype=torch.float64)
+    ins = torch.zeros(n, dtype=torch.uint8)
+    cases = [
+        (good.float(), out, ins, "float64"),
+        (torch.zeros((n, 3), dtype=torch.float64), out, ins, "shape"),
+        (torch.zeros(2 * n, dtype=torch.float64), out, ins, "[n, 2]"),
+        (torch.zeros((n, 4), dtype=torch.float64)[:, ::2], out, ins, "contiguous"),
+        (good, torch.zeros(n - 1, dtype=torch.float64), ins, "shape"),
+        (good, out.float(), ins, "float64"),
+        (good, out, torch.zeros(n, dtype=torch.int32), "uint8"),
+        (good, out, torch.zeros(n + 1, dtype=torch.uint8), "shape"),
+        (good, out, ins, "GPU"),
+        (np.zeros((n, 2)), out, ins, "tensor"),
+    ]
+    for pts, o, i, msg in cases:
+        for fn in (G.gwn_query,):
+            with pytest.raises(ValueError, match=msg):
+                fn(h, pts, o, i)
+    with pytest.raises(ValueError, match="counters"):
+        G.gwn_query_counters(h, good, torch.zeros(3, dtype=torch.int64))
+    with pytest.raises(ValueError, match="n_seg"):
+        G.gwn_query_batch([h, h], np.array([0, n]), good, out, ins)
+    with pytest.raises(ValueError, match="non-decreasing"):
+        G.gwn_query_batch([h, h], np.array([0, 6, 4]), good, out, ins)
+    with pytest.raises(ValueError, match="shape"):
+        G.gwn_query_batch([h, h], np.array([0, 4, 12]), good, out, ins)
+    P = W.Patches3D.from_list([(cp, w, []) for cp, w in W.bodies(0, [("sphere", (0, 0, 0), 1.0)], disp=0.0)][:4])
+    h3 = G.gwn_build3d(P, host_params())
+    with pytest.raises(ValueError, match="one dimension"):
+        G.gwn_query_batch([h, h3], np.array([0, 4, 8]), good, out, ins)
+    with pytest.raises(ValueError, match="shape"):
+        G.gwn_query(h3, good, out, ins)
+    G.gwn_free(h)
+    G.gwn_free(h3)
+
+
+def test_overflow_count_semantics_documented():
+    """The device overflow count is never reset; the header states that
+    each overflowing call is reported once, by a later call."""
+    src = open(os.path.join(ROOT, "include", "gwn.h")).read()
+    assert "reported once" in src

@@ -107,3 +107,59 @@ def test_bad_requests():
     with pytest.raises(ValueError):
         s.run([serve.Request(0, np.zeros((4, 3)))])
     s.close()
+
+
+def test_submit_from_live_producer(models2d):
+    """A producer thread submits requests while earlier ones are in flight;
+    every future resolves to the request's solo values, and an invalid
+    request fails its own future only."""
+    import threading
+    s = serve.Server(budget_bytes=256 << 20, n_slots=2, chunk=1 << 14)
+    for g, p in models2d:
+        s.add_model(g, p)
+    rng = W.Rng(64, "submit")
+    sizes = [5, 3000, 64, 20000, 1, 777, 40000, 130]
+    jobs = []
+
+    def producer():
+        for i, n in enumerate(sizes):
+            m = i % len(models2d)
+            lo, hi = models2d[m][0].bbox()
+            pts = W.bbox_queries_uniform(rng, lo, hi, n, 1.2)
+            jobs.append((m, pts, s.submit(m, pts)))
+
+    t = threading.Thread(target=producer)
+    t.start()
+    t.join()
+    bad = s.submit(7, np.zeros((3, 2)))
+    for m, pts, f in jobs:
+        w, ins = f.result(timeout=120)
+        ws, inss = solo(s.models[m], pts)
+        assert np.array_equal(w, ws) and np.array_equal(ins, inss)
+    with pytest.raises(ValueError):
+        bad.result(timeout=60)
+    s.close()
+
+
+def test_launches_overlap_on_device():
+    """Closed-loop requests on four slots against a 3D model (each launch's
+    device work far longer than the host's preparation of the next): HIP
+    events on the slot streams show launches of different slots in flight
+    at the same time."""
+    from itertools import combinations
+    s = serve.Server(budget_bytes=4 << 30, n_slots=4, chunk=1 << 13, max_launch=1 << 14, record_timing=True)
+    g = W.cad_assembly(63, n_bodies=2)
+    s.add_model(g, presets.params(presets.FP64_3D))
+    lo, hi = g.bbox()
+    rng = W.Rng(65, "overlap")
+    reqs = [serve.Request(0, W.bbox_queries_uniform(rng, lo, hi, 16_000, 1.1)) for _ in range(8)]
+    s.run(reqs, closed_loop=True)
+    iv = s.launch_intervals()
+    assert len(iv) >= 8 and all(b > a for _, a, b in iv)
+    pairs = [(x, y) for x, y in combinations(iv, 2) if x[0] != y[0] and x[1] < y[2] and y[1] < x[2]]
+    print(f"serve overlap: {len(iv)} launches, {len(pairs)} overlapping pairs on different slots", flush=True)
+    assert pairs
+    for r in reqs:
+        w, ins = solo(s.models[0], r.points)
+        assert np.array_equal(r.w, w) and np.array_equal(r.inside, ins)
+    s.close()
