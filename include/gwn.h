@@ -230,6 +230,24 @@ gwn_status gwn_get_params(gwn_handle h, gwn_params *out);
 gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
                      uint8_t *out_inside, void *stream);
 
+/* gwn_query for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bitwise) as gwn_query, but the launch's
+ * scratch (sort keys and permutation, sort temporaries, 3D near-field
+ * records) is a fixed array of GWN_NOALLOC_SCRATCH_BYTES in device memory,
+ * one per GPU, reserved by the library from its first such call on that GPU
+ * until the process ends.  The call makes no hipMalloc / hipFree and no
+ * other allocation.  All calls on one GPU share that array and it keeps the
+ * last call's contents (nothing in it needs clearing: every record is
+ * written before it is read); calls that overlap on one GPU -- e.g. on two
+ * streams -- race on it and must be serialised by the caller.  A call whose
+ * scratch (gwn_query_scratch_bytes(h, n, 1, ...)) exceeds the array fails
+ * with GWN_EINVAL before any launch: about 3.5M queries fit in 2D, about
+ * 320k in 3D. */
+#define GWN_NOALLOC_SCRATCH_BYTES ((int64_t)96 << 20)
+gwn_status gwn_query_noalloc(gwn_handle h, const double *points, int64_t n, double *out_gwn,
+                             uint8_t *out_inside, void *stream);
+
 /* Device scratch bytes one gwn_query / gwn_query_batch call takes at once for
  * n query rows in n_seg segments (exact for n_seg = 1, an upper bound
  * otherwise), for admission by memory budget.  Host-only; needs a HIP

@@ -453,7 +453,7 @@ static gwn_status after_launch(Model &m, void *stream)
 }
 
 static gwn_status query_common(gwn_handle h, const double *points, int64_t n, double *out_gwn,
-                               uint8_t *out_inside, void *stream)
+                               uint8_t *out_inside, void *stream, bool fixed_scratch)
 {
     if (!h) return fail(GWN_EINVAL, "NULL handle");
     if (n < 0) return fail(GWN_EINVAL, "n < 0");
@@ -467,6 +467,17 @@ static gwn_status query_common(gwn_handle h, const double *points, int64_t n, do
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     std::string err;
     ExtScratch ext;
+    if (fixed_scratch) {
+        s = noalloc_scratch(ext, err);
+        if (s) return fail(s, err);
+        int64_t need = 0;
+        s = query_scratch_bytes(h->m.dim, n, 1, need, err);
+        if (s) return fail(s, err);
+        if ((size_t)need > ext.bytes)
+            return fail(GWN_EINVAL, std::to_string(n) + " queries need " + std::to_string(need) +
+                                        " bytes of scratch, above the fixed " + std::to_string(ext.bytes) +
+                                        " (GWN_NOALLOC_SCRATCH_BYTES); split the call");
+    }
     std::vector<Segment> segs{{&h->m, 0, n}};
     s = launch_queries(segs, h->m.dim, points, out_gwn, out_inside, nullptr, stream, err, ext);
     if (s) return fail(s, err);
@@ -476,7 +487,13 @@ static gwn_status query_common(gwn_handle h, const double *points, int64_t n, do
 extern "C" gwn_status gwn_query(gwn_handle h, const double *points, int64_t n, double *out_gwn,
                                 uint8_t *out_inside, void *stream)
 {
-    return query_common(h, points, n, out_gwn, out_inside, stream);
+    return query_common(h, points, n, out_gwn, out_inside, stream, false);
+}
+
+extern "C" gwn_status gwn_query_noalloc(gwn_handle h, const double *points, int64_t n, double *out_gwn,
+                                        uint8_t *out_inside, void *stream)
+{
+    return query_common(h, points, n, out_gwn, out_inside, stream, true);
 }
 
 extern "C" gwn_status gwn_query_scratch_bytes(gwn_handle h, int64_t n, int32_t n_seg, int64_t *bytes)

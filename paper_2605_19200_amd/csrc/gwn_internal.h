@@ -270,17 +270,21 @@ struct Segment {
     const Model *model;
     int64_t q_begin, q_end;   // rows of the points/output arrays
 };
-// Scratch handed to a launch instead of stream-ordered allocation;
-// ptr == nullptr: allocate from the pool.
+// Scratch handed to a launch instead of stream-ordered allocation (the entry
+// point that allocates nothing); ptr == nullptr: allocate from the pool.
 struct ExtScratch {
     void *ptr = nullptr;
     size_t bytes = 0;
 };
+constexpr size_t kNoAllocScratchBytes = (size_t)96 << 20;   // per GPU
+constexpr int kMaxDevices = 64;
 gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const double *points,
                           double *out_gwn, uint8_t *out_inside, int64_t *counters, void *stream,
                           std::string &err, const ExtScratch &ext = ExtScratch{});
 // Scratch bytes of one query call over n rows in n_seg segments (an upper
 // bound; exact for one segment).
 gwn_status query_scratch_bytes(int dim, int64_t n, int32_t n_seg, int64_t &bytes, std::string &err);
+// This device's fixed scratch array (address looked up once per device).
+gwn_status noalloc_scratch(ExtScratch &out, std::string &err);
 
 }  // namespace gwn

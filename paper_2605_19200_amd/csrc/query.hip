@@ -754,4 +754,38 @@ gwn_status query_scratch_bytes(int dim, int64_t n, int32_t n_seg, int64_t &bytes
     return GWN_OK;
 }
 
+// Fixed scratch of the entry point that allocates nothing: one array per
+// GPU, held from the library's first such call on that GPU to the end of the
+// process.  Host code never uses the array's name as an address (on the host
+// it only names the symbol): the device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+gwn_status noalloc_scratch(ExtScratch &out, std::string &err)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_err(e, "hipGetDevice", err);
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "device ordinal " + std::to_string(dev) + " beyond the fixed-scratch table";
+        return GWN_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_err(e, "hipGetSymbolAddress(scratch)", err);
+        if (!p) {
+            err = "hipGetSymbolAddress(scratch) returned NULL";
+            return GWN_EHIP;
+        }
+        addr[dev] = p;
+    }
+    out.ptr = addr[dev];
+    out.bytes = kNoAllocScratchBytes;
+    return GWN_OK;
+}
+
 }  // namespace gwn

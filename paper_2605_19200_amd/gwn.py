@@ -24,9 +24,10 @@ GWN_NCOUNTERS = len(COUNTER_NAMES)
  GWN_I_FARBETA) = range(8)
 
 EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
-            "gwn_get_params", "gwn_query", "gwn_query_scratch_bytes",
+            "gwn_get_params", "gwn_query", "gwn_query_noalloc", "gwn_query_scratch_bytes",
             "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
             "gwn_free", "gwn_last_error"]
+GWN_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 
 class GwnError(RuntimeError):
@@ -81,6 +82,7 @@ def lib():
             ("gwn_set_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_get_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_query", [vp, vp, i64, vp, vp, vp]),
+            ("gwn_query_noalloc", [vp, vp, i64, vp, vp, vp]),
             ("gwn_query_scratch_bytes", [vp, i64, i32, ctypes.POINTER(i64)]),
             ("gwn_query_batch", [i32, vp, vp, vp, vp, vp, vp]),
             ("gwn_query_counters", [vp, vp, i64, vp, vp]),
@@ -264,6 +266,12 @@ def gwn_query(h, points, out_gwn, out_inside=None, stream=None):
     """points: device float64 tensor [n, dim]; out_gwn: device float64 [n];
     out_inside: device uint8 [n] or None.  Asynchronous on `stream`."""
     _query_call(lib().gwn_query, h, points, out_gwn, out_inside, stream)
+
+
+def gwn_query_noalloc(h, points, out_gwn, out_inside=None, stream=None):
+    """As gwn_query, with the launch's scratch in the library's fixed
+    per-GPU array (no device allocation; calls overlapping on one GPU race)."""
+    _query_call(lib().gwn_query_noalloc, h, points, out_gwn, out_inside, stream)
 
 
 def gwn_query_scratch_bytes(h, n: int, n_seg: int = 1) -> int:

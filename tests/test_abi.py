@@ -134,7 +134,7 @@ def test_query_arguments_checked_before_any_launch():
         (np.zeros((n, 2)), out, ins, "tensor"),
     ]
     for pts, o, i, msg in cases:
-        for fn in (G.gwn_query,):
+        for fn in (G.gwn_query, G.gwn_query_noalloc):
             with pytest.raises(ValueError, match=msg):
                 fn(h, pts, o, i)
     with pytest.raises(ValueError, match="counters"):
