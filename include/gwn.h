@@ -319,13 +319,19 @@ gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_s
  *                   Re(I_l^m N_l^m)] with I_l^m(q - c) = (l - m)!
  *                   P_l^m(cos t) e^{i m p} / |q - c|^(l+1).  The order-p far
  *                   field (Eq. taylor) is the truncation l <= p + 1.
+ *   GWN_I_LEAF_TRIMS 3D only, per trim curve of every leaf, leaf by leaf (BVH
+ *                   leaf order): leaf index, then the curve's homogeneous
+ *                   control points (w u, w v, w) x 3 in the leaf's own
+ *                   parameter square -- 10 doubles.  A leaf cut from a
+ *                   trimmed patch holds its clipped loops (closed, in loop
+ *                   order); an untrimmed leaf has none.
  *   GWN_I_FARBETA   2D only, per node: the far-field factor the FP64 test
  *                   uses under the handle's current parameters -- beta, or
  *                   with far_tol > 0 the cluster's own beta_c (+inf when no
  *                   factor meets the budget); 0 for leaves.  1 double.
  */
 enum { GWN_I_SUMMARY = 0, GWN_I_LEAVES = 1, GWN_I_NODES = 2, GWN_I_MOMENTS = 3, GWN_I_UNCENTERED = 4,
-       GWN_I_COMPLEX = 5, GWN_I_MULTIPOLE = 6, GWN_I_FARBETA = 7 };
+       GWN_I_COMPLEX = 5, GWN_I_MULTIPOLE = 6, GWN_I_FARBETA = 7, GWN_I_LEAF_TRIMS = 8 };
 gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64_t capacity, int64_t *count);
 
 /* Kernel timing.  gwn_profile(1, NULL, NULL) starts recording a pair of HIP

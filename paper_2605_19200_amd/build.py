@@ -21,7 +21,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 
-SOURCES = ["capi.cpp", "tree.cpp", "build2d.cpp", "build3d.cpp", "nurbs.cpp", "moments2d.hip", "lbvh.hip", "query.hip", "query3d.hip"]
+SOURCES = ["capi.cpp", "tree.cpp", "build2d.cpp", "build3d.cpp", "trimclip.cpp", "nurbs.cpp", "moments2d.hip", "lbvh.hip",
+           "query.hip", "query3d.hip"]
 
 
 def _compile(src: str) -> str:

@@ -64,7 +64,7 @@ namespace {
 struct Patch {
     double h[4][4][4];   // [i along u][j along v][wx, wy, wz, w]
     int64_t src;
-    int trim_begin = 0, trim_count = 0;   // into the model's trim array
+    std::vector<Trim3> trims;   // closed loops in the patch's own (u, v); empty = whole square
 };
 
 void cubic_basis(double t, double *B, double *dB)
@@ -123,17 +123,19 @@ void patch_aabb(const Patch &p, double lo[3], double hi[3])
             }
 }
 
-// de Casteljau bisection of the control net at 1/2 along u (dir 0) or v.
-void split(const Patch &p, int dir, Patch &L, Patch &R)
+// de Casteljau split of the control net at parameter t along u (dir 0) or
+// v; each half is reparametrised to [0, 1].
+void split(const Patch &p, int dir, double t, Patch &L, Patch &R)
 {
     L = p;
     R = p;
+    const double s = 1.0 - t;
     for (int a = 0; a < 4; ++a)
         for (int k = 0; k < 4; ++k) {
             double c[4];
             for (int i = 0; i < 4; ++i) c[i] = dir == 0 ? p.h[i][a][k] : p.h[a][i][k];
-            double b0 = 0.5 * (c[0] + c[1]), b1 = 0.5 * (c[1] + c[2]), b2 = 0.5 * (c[2] + c[3]);
-            double c0 = 0.5 * (b0 + b1), c1 = 0.5 * (b1 + b2), d0 = 0.5 * (c0 + c1);
+            double b0 = s * c[0] + t * c[1], b1 = s * c[1] + t * c[2], b2 = s * c[2] + t * c[3];
+            double c0 = s * b0 + t * b1, c1 = s * b1 + t * b2, d0 = s * c0 + t * c1;
             double l[4] = {c[0], b0, c0, d0}, r[4] = {d0, c1, b2, c[3]};
             for (int i = 0; i < 4; ++i) {
                 (dir == 0 ? L.h[i][a][k] : L.h[a][i][k]) = l[i];
@@ -226,7 +228,6 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
             err = "NULL trim array";
             return GWN_EINVAL;
         }
-        pt.trim_begin = (int)m.trims.size();
         double ls[2] = {0, 0}, pe[2] = {0, 0};
         bool open = false;
         for (int64_t k = t0; k < t1; ++k) {
@@ -271,11 +272,10 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
                     tr.h[6 + q] = P[1][q];
                 }
             }
-            m.trims.push_back(tr);
+            pt.trims.push_back(tr);
         }
         if (open) { err = "patch " + std::to_string(i) + ": trim loop is not closed"; return GWN_EINVAL; }
-        pt.trim_count = (int)(t1 - t0);
-        work.push_back(pt);
+        work.push_back(std::move(pt));
     }
     if (n == 0)
         for (int k = 0; k < 3; ++k) lo[k] = hi[k] = 0.0;
@@ -287,37 +287,53 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     }
     m.diag = std::sqrt(diag2);
 
-    // AdaptiveSubdivision (Sec. 3.2): bisect untrimmed patches while their
-    // AABB diagonal is not below max_diag_frac of the model diagonal, in the
+    // AdaptiveSubdivision (Sec. 3.2): bisect patches while their AABB
+    // diagonal is not below max_diag_frac of the model diagonal, in the
     // parameter direction whose middle iso-curve has the longer control
-    // polygon.  Trimmed patches are kept whole (splitting them would need
-    // their trim loops clipped to each half), and so are patches with an
-    // edge collapsed to a point: the near-field rule resolves the whole
-    // polar patch, while its sub-patches at the pole put the foot point on a
-    // degenerate corner of a tiny, strongly non-uniform domain.
+    // polygon.  A trimmed patch's loops are clipped to each half and mapped
+    // to the half's unit square (clip_trims_half); a half that holds none of
+    // the visible region is dropped.  When the cut at 1/2 would pass through
+    // a junction of two trim curves or touch a loop tangentially, the cut
+    // moves to the nearest of 1/2 +- k/64 (k = 1..8) where it does not.
+    // Patches with an edge collapsed to a point are kept whole: the
+    // near-field rule resolves the whole polar patch, while its sub-patches
+    // at the pole put the foot point on a degenerate corner of a tiny,
+    // strongly non-uniform domain.
     const double limit = p->max_diag_frac * m.diag;
     std::vector<Patch> leaves;
     leaves.reserve(work.size());
     struct Item { Patch p; int depth; };
     std::vector<Item> st;
-    for (int64_t i = (int64_t)work.size() - 1; i >= 0; --i) st.push_back({work[i], 0});
+    for (int64_t i = (int64_t)work.size() - 1; i >= 0; --i) st.push_back({std::move(work[i]), 0});
+    std::vector<Trim3> lo_trims, hi_trims;
     while (!st.empty()) {
-        Item it = st.back();
+        Item it = std::move(st.back());
         st.pop_back();
         double l[3], h[3];
         patch_aabb(it.p, l, h);
         const double dg = std::sqrt((h[0] - l[0]) * (h[0] - l[0]) + (h[1] - l[1]) * (h[1] - l[1]) +
                                     (h[2] - l[2]) * (h[2] - l[2]));
-        if (limit > 0 && dg >= limit && it.p.trim_count == 0 && it.depth < 24 &&
-            !has_collapsed_edge(it.p, 1e-12 * m.diag)) {
+        bool done = true;
+        if (limit > 0 && dg >= limit && it.depth < 24 && !has_collapsed_edge(it.p, 1e-12 * m.diag)) {
             const int dir = mid_iso_length(it.p, 0) >= mid_iso_length(it.p, 1) ? 0 : 1;
-            Patch L, R;
-            split(it.p, dir, L, R);
-            st.push_back({R, it.depth + 1});
-            st.push_back({L, it.depth + 1});
-        } else {
-            leaves.push_back(it.p);
+            for (int k = 0; k <= 16; ++k) {
+                const double c = 0.5 + (k == 0 ? 0.0 : ((k & 1) ? 1.0 : -1.0) * ((k + 1) / 2) / 64.0);
+                if (!it.p.trims.empty() && (!clip_trims_half(it.p.trims, dir, c, true, lo_trims) ||
+                                            !clip_trims_half(it.p.trims, dir, c, false, hi_trims)))
+                    continue;
+                Patch L, R;
+                split(it.p, dir, c, L, R);
+                const bool trimmed = !it.p.trims.empty();
+                L.trims = trimmed ? lo_trims : std::vector<Trim3>{};
+                R.trims = trimmed ? hi_trims : std::vector<Trim3>{};
+                // an empty loop list of a trimmed patch's half: nothing visible
+                if (!trimmed || !R.trims.empty()) st.push_back({std::move(R), it.depth + 1});
+                if (!trimmed || !L.trims.empty()) st.push_back({std::move(L), it.depth + 1});
+                done = false;
+                break;
+            }
         }
+        if (done) leaves.push_back(std::move(it.p));
     }
     const int nl = (int)leaves.size();
 
@@ -348,7 +364,7 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         patch_aabb(pt, &LO[3 * li], &HI[3 * li]);
         // boundary curves: the trims, or the edge u = 1 of the square
         std::vector<Trim3> curves;
-        if (pt.trim_count == 0) {
+        if (pt.trims.empty()) {
             Trim3 e;
             std::memset(&e, 0, sizeof e);
             const double P[3][3] = {{1, 0, 1}, {1, 0.5, 1}, {1, 1, 1}};
@@ -356,7 +372,7 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
                 for (int q = 0; q < 3; ++q) e.h[3 * j + q] = P[j][q];
             curves.push_back(e);
         } else {
-            curves.assign(m.trims.begin() + pt.trim_begin, m.trims.begin() + pt.trim_begin + pt.trim_count);
+            curves = pt.trims;
         }
         double *u_out = &U[(size_t)li * nm];
         // scatter no x ni nodes per boundary curve (no along the curve, ni
@@ -474,8 +490,9 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
             for (int i = 0; i < 4; ++i)
                 for (int j = 0; j < 4; ++j)
                     for (int k = 0; k < 4; ++k) m.leaf_h.push_back(pt.h[i][j][k]);
-            m.leaf_trim_begin.push_back(pt.trim_begin);
-            m.leaf_trim_count.push_back(pt.trim_count);
+            m.leaf_trim_begin.push_back((int32_t)m.trims.size());
+            m.leaf_trim_count.push_back((int32_t)pt.trims.size());
+            m.trims.insert(m.trims.end(), pt.trims.begin(), pt.trims.end());
             m.leaf_q_begin.push_back((int64_t)m.qnodes.size());
             m.leaf_q_count.push_back((int64_t)qn[src].size());
             m.leaf_q_rules.push_back(qcount[src]);

@@ -635,6 +635,19 @@ extern "C" gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64
         }
         break;
     }
+    case GWN_I_LEAF_TRIMS: {
+        if (d != 3) return fail(GWN_EINVAL, "trim curves exist for 3D models only");
+        width = 10;
+        items = (int64_t)m.trims.size();
+        buf.resize(items * width);
+        int64_t k = 0;
+        for (size_t l = 0; l < m.leaf_trim_begin.size(); ++l)
+            for (int32_t j = 0; j < m.leaf_trim_count[l]; ++j, ++k) {
+                buf[k * width] = (double)l;
+                std::memcpy(&buf[k * width + 1], m.trims[m.leaf_trim_begin[l] + j].h, sizeof(double) * 9);
+            }
+        break;
+    }
     case GWN_I_MULTIPOLE: {
         if (d != 3) return fail(GWN_EINVAL, "multipole moments exist for 3D models only");
         width = kMpoleStride;

@@ -260,6 +260,12 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
 // invalid input
 bool extract_nurbs2d(const gwn_nurbs2d &in, std::vector<int32_t> &deg, std::vector<int64_t> &off,
                      std::vector<double> &xy, std::vector<double> &w, std::string &err);
+// Clip the closed trim loops `in` of a patch's visible region to the half
+// x_dir <= c (low) or >= c of the unit square and map them to the half's
+// own unit square (trimclip.cpp).  false: the cut passes through a junction
+// of two trim curves or touches a loop tangentially (move the cut).  An
+// empty `out` means the half holds none of the visible region.
+bool clip_trims_half(const std::vector<Trim3> &in, int dir, double c, bool low, std::vector<Trim3> &out);
 // upload to device and fill m.dev
 gwn_status upload_model(Model &m, std::string &err);
 void refresh_dev_params(Model &m);

@@ -21,7 +21,7 @@ GWN_FP64, GWN_MIXED = 0, 1
 COUNTER_NAMES = ["nodes", "far", "leaves", "leaf_fast", "pieces", "angles", "reclass", "overflow"]
 GWN_NCOUNTERS = len(COUNTER_NAMES)
 (GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX, GWN_I_MULTIPOLE,
- GWN_I_FARBETA) = range(8)
+ GWN_I_FARBETA, GWN_I_LEAF_TRIMS) = range(9)
 
 EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
             "gwn_get_params", "gwn_query", "gwn_query_noalloc", "gwn_query_scratch_bytes",
@@ -327,7 +327,8 @@ def gwn_model_bytes(h):
 
 _WIDTH = {GWN_I_SUMMARY: lambda d: 8, GWN_I_LEAVES: lambda d: 13 if d == 2 else 65, GWN_I_NODES: lambda d: 13,
           GWN_I_MOMENTS: lambda d: d + d * d + d ** 3, GWN_I_UNCENTERED: lambda d: d + d * d + d ** 3,
-          GWN_I_COMPLEX: lambda d: 34, GWN_I_MULTIPOLE: lambda d: 72, GWN_I_FARBETA: lambda d: 1}
+          GWN_I_COMPLEX: lambda d: 34, GWN_I_MULTIPOLE: lambda d: 72, GWN_I_FARBETA: lambda d: 1,
+          GWN_I_LEAF_TRIMS: lambda d: 10}
 
 
 def gwn_inspect(h, what: int) -> np.ndarray:

@@ -55,14 +55,34 @@ def test_subdivision_of_large_patch_and_moment_sum():
     assert np.abs(split - whole).max() < 1e-10 * np.abs(whole).max()
 
 
-def test_trimmed_patch_not_split_and_validation():
+def leaf_patches(P, **kw):
+    """The leaves of a host-only build as a patch set of their own: each
+    leaf's control net and its clipped trim loops in its own square."""
+    h = G.gwn_build3d(P, G.gwn_default_params(device=-1, **kw))
+    leaves = G.gwn_inspect(h, G.GWN_I_LEAVES)
+    trims = G.gwn_inspect(h, G.GWN_I_LEAF_TRIMS)
+    G.gwn_free(h)
+    items = []
+    for l in range(leaves.shape[0]):
+        net = leaves[l, 1:].reshape(4, 4, 4)
+        cp, wt = net[..., :3] / net[..., 3:4], net[..., 3]
+        mine = trims[trims[:, 0] == l, 1:].reshape(-1, 3, 3)
+        tl = [(c[:, :2] / c[:, 2:3], c[:, 2].copy()) for c in mine]
+        items.append((cp, wt, tl))
+    return W.Patches3D.from_list(items), leaves[:, 0].astype(int)
+
+
+def test_trimmed_patch_split_and_validation():
     cp, w = bilinear_patch((0, 0, 0), (4, 0, 0), (4, 4, 0), (0, 4, 0))
     trims = W.square_trim() + W.circle_trim((0.5, 0.5), 0.2)
-    B = build(patches((cp, w, trims), (*bilinear_patch((5, 5, 5), (5.1, 5, 5), (5.1, 5.1, 5), (5, 5.1, 5)), [])))
-    assert np.sum(B["leaves"][:, 0] == 0) == 1
-    # flat square with a hole: int n dA = (area of square - hole) * normal, exact up to quadrature
-    U = build(patches((cp, w, trims)))["U"][0]
-    assert abs(U[2] - 16 * (1 - math.pi * 0.04)) < 1e-9 and abs(U[0]) < 1e-12 and abs(U[1]) < 1e-12
+    small = bilinear_patch((5, 5, 5), (5.1, 5, 5), (5.1, 5.1, 5), (5, 5.1, 5))
+    B = build(patches((cp, w, trims), (*small, [])))
+    assert np.sum(B["leaves"][:, 0] == 0) > 4 and np.sum(B["leaves"][:, 0] == 1) == 1
+    # flat square with a hole: int n dA = (area of square - hole) * normal,
+    # exact up to quadrature, whether the patch is split or not
+    for frac in (10.0, 0.1):
+        U = build(patches((cp, w, trims)), max_diag_frac=frac)["U"][0]
+        assert abs(U[2] - 16 * (1 - math.pi * 0.04)) < 1e-9 and abs(U[0]) < 1e-12 and abs(U[1]) < 1e-12
     for bad in ["open", "outside", "degree"]:
         t = [(uv.copy(), wt.copy()) for uv, wt in trims]
         if bad == "open":
@@ -74,6 +94,52 @@ def test_trimmed_patch_not_split_and_validation():
         with pytest.raises(G.GwnError) as ei:
             build(patches((cp, w, t)))
         assert ei.value.status == G.GWN_EINVAL
+
+
+def test_trimmed_subdivision_leaves_sum_to_the_original(oracle):
+    """Subdivision leaves the ground-truth GWN unchanged (Sec. 4.2): the
+    leaves of split trimmed patches -- control nets cut by de Casteljau,
+    trim loops clipped to each half and mapped to its square, halves with
+    nothing visible dropped -- are closed valid loops, and the oracle's sum
+    over them equals its value for the original patches.  Cases: a warped
+    patch with three holes (one of them crossed by the first cuts), a
+    sphere patch with a hole, and a patch whose visible region is a disk
+    only (so some halves are empty)."""
+    rng = W.Rng(37, "clip")
+    cp, w = bilinear_patch((0, 0, 0), (2, 0, 0.3), (2, 2, -0.2), (0, 2, 0.1), w=[[1.0, 1.4], [0.8, 1.2]])
+    cp = cp + 0.15 * rng.uniform((4, 4, 3), -1, 1)
+    holes = W.square_trim() + W.circle_trim((0.5, 0.62), 0.12) + W.circle_trim((0.25, 0.25), 0.1) + \
+        W.circle_trim((0.72, 0.3), 0.15)
+    sph = W.bodies(0, [("sphere", (3, 0, 0), 1.0)], disp=0.0)[200]
+    disk_only = bilinear_patch((0, 3, 0), (1, 3, 0), (1, 4, 0.4), (0, 4, 0.2))
+    P = patches((cp, w, holes), (*sph, W.square_trim() + W.circle_trim((0.4, 0.55), 0.3)),
+                (*disk_only, W.circle_trim((0.3, 0.35), 0.2, ccw=True)))
+    L, src = leaf_patches(P, max_diag_frac=0.02)
+    counts = np.bincount(src, minlength=3)
+    assert np.all(counts >= 8), counts
+    lo, hi = P.bbox()
+    q = np.concatenate([W.bbox_queries_uniform(rng, lo, hi, 24, 1.2),
+                        W.near_surface_queries(P, rng, 24, t_max=1e-3)])
+    eps = oracle.default_eps_on(lo, hi)
+    ref = oracle.gwn3d(P, q, eps_on=eps)
+    got = oracle.gwn3d(L, q, eps_on=eps)
+    assert np.abs(got - ref).max() < 1e-10, np.abs(got - ref).max()
+
+
+def test_cad_assembly_trimmed_patches_are_split():
+    """Every patch of the CAD assembly is trimmed; at the presets'
+    subdivision they are split like untrimmed ones (more leaves than
+    patches), and the root's uncentered moments -- sums over the leaves'
+    visible parts -- equal those of the unsplit build."""
+    from paper_2605_19200_amd import presets
+    P = W.cad_assembly(4, n_bodies=6)
+    frac = presets.FP64_3D["max_diag_frac"]
+    whole = build(P, max_diag_frac=10.0)
+    split = build(P, max_diag_frac=frac)
+    assert split["summary"][0][2] > 1.3 * P.n, (split["summary"][0][2], P.n)
+    # uncentered moments of the root are sums over the leaves: unchanged
+    Uw, Us = whole["U"][0], split["U"][0]
+    assert np.abs(Us - Uw).max() < 1e-9 * np.abs(Uw).max()
 
 
 def test_upsweep_and_centering_3d():
