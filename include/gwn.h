@@ -140,10 +140,15 @@ typedef struct {
                               panels) when dist(q, AABB) < near_ratio * AABB
                               diagonal (default 0.25); farther leaves use their
                               precomputed Gauss-Legendre node sets            */
-    double eps_q;          /* Q, 3D: reserved.  Validated (> 0) and stored; the
-                              near-field rule has a fixed node budget, checked
-                              to ~1e-9 per leaf, so the value does not change
-                              results (default 1e-10)                         */
+    double eps_q;          /* Q, 3D: tolerance of a leaf's direct evaluation by
+                              the near-field rule, in units of w (Sec. 3.3;
+                              default 1e-6, the paper's value for the
+                              accelerated method, Sec. 4.2).  Each panel and
+                              radial piece carries a Gauss-Kronrod error
+                              estimate; a leaf is refined until the estimates
+                              meet eps_q, and a leaf that cannot meet it
+                              within its refinement budget makes its query NaN
+                              and is reported as GWN_EOVERFLOW              */
     int32_t leaf_far;      /* Q, 3D: 1 = a leaf reached by the traversal that
                               passes the far test ||q - c|| > beta * r itself is
                               evaluated by its own far-field expansion, like a

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstring>
 #include <thread>
+#include <vector>
 
 #include "gwn_internal.h"
 #include "multipole3d.h"
@@ -57,6 +58,111 @@ void gauss_legendre01(int n, double *x, double *w)
         x[n - 1 - i] = 0.5 * (z + 1.0);
         w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);   // (2 / (...)) / 2 for [0, 1]
     }
+}
+
+// The (2n+1)-point Gauss-Kronrod rule on [0, 1] with its embedded n-point
+// Gauss rule (2 <= n <= 10), computed from the definition (Kronrod 1965):
+// the n + 1 added nodes are the zeros of the Stieltjes polynomial E_{n+1},
+// the monic polynomial of degree n + 1 orthogonal to every polynomial of
+// degree <= n under the weight P_n on [-1, 1]; E_{n+1} has the parity of
+// n + 1, and its zeros interlace the Gauss nodes.  The weights make the rule
+// exact for polynomials of degree <= 2n, which with those nodes makes it
+// exact to degree 3n + 1.  Nodes are returned in increasing order; the Gauss
+// nodes are the odd indices and wg[i] is the Gauss weight of node 2 i + 1.
+void gauss_kronrod01(int n, double *xk, double *wk, double *wg)
+{
+    typedef long double R;
+    // power-basis coefficients of P_n by the three-term recurrence
+    R pm[12] = {1}, pc[12] = {0, 1}, pn[12];
+    for (int k = 2; k <= n; ++k) {
+        for (int i = 0; i <= k; ++i) {
+            pn[i] = -(R)(k - 1) / k * (i < k - 1 ? pm[i] : 0);
+            if (i > 0) pn[i] += (R)(2 * k - 1) / k * pc[i - 1];
+        }
+        for (int i = 0; i < 12; ++i) { pm[i] = pc[i]; pc[i] = i <= k ? pn[i] : 0; }
+    }
+    const R *pol = pc;
+    auto mom = [&](int m) {   // integral over [-1, 1] of P_n(x) x^m
+        R s = 0;
+        for (int i = 0; i <= n; ++i)
+            if (pol[i] != 0 && (i + m) % 2 == 0) s += pol[i] * 2 / (R)(i + m + 1);
+        return s;
+    };
+    // E_{n+1}(x) = x^(n+1) + sum_j a_j x^(n+1-2-2j): unknown coefficients of
+    // the powers of its parity below n + 1, one condition per odd k <= n
+    const int nu = (n + 1) / 2;
+    R A[6][7];
+    for (int r = 0; r < nu; ++r) {
+        const int k = 2 * r + 1;
+        for (int c = 0; c < nu; ++c) A[r][c] = mom((n + 1) % 2 + 2 * c + k);
+        A[r][nu] = -mom(n + 1 + k);
+    }
+    for (int c = 0; c < nu; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < nu; ++r)
+            if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+        for (int j = 0; j <= nu; ++j) std::swap(A[c][j], A[piv][j]);
+        for (int r = 0; r < nu; ++r)
+            if (r != c) {
+                const R f = A[r][c] / A[c][c];
+                for (int j = c; j <= nu; ++j) A[r][j] -= f * A[c][j];
+            }
+    }
+    R a[6];
+    for (int c = 0; c < nu; ++c) a[c] = A[c][nu] / A[c][c];   // coefficient of x^((n+1)%2 + 2c)
+    auto E = [&](R x) {
+        R s = powl(x, n + 1);
+        for (int c = 0; c < nu; ++c) s += a[c] * powl(x, (n + 1) % 2 + 2 * c);
+        return s;
+    };
+    double gx[10], gw[10];
+    gauss_legendre01(n, gx, gw);
+    // nonnegative nodes: Gauss ones from the n-point rule, Kronrod ones one in
+    // each gap above a Gauss node (and 0 when n is even)
+    std::vector<R> gpos, kpos;
+    for (int i = 0; i < n; ++i) {
+        const R x = 2 * (R)gx[i] - 1;
+        if (x > -1e-30L) gpos.push_back(x < 1e-30L ? 0 : x);
+    }
+    std::sort(gpos.begin(), gpos.end());
+    if (n % 2 == 0) kpos.push_back(0);
+    for (size_t i = 0; i < gpos.size(); ++i) {
+        R lo = gpos[i], hi = i + 1 < gpos.size() ? gpos[i + 1] : 1;
+        R flo = E(lo);
+        for (int it = 0; it < 200; ++it) {
+            const R mid = (lo + hi) / 2, fm = E(mid);
+            if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
+        }
+        kpos.push_back((lo + hi) / 2);
+    }
+    std::vector<R> ys;   // distinct |x|^2, the centre first
+    for (R x : gpos) ys.push_back(x * x);
+    for (R x : kpos) ys.push_back(x * x);
+    std::sort(ys.begin(), ys.end());
+    const int m = (int)ys.size();   // n + 1
+    R V[12][13];
+    for (int j = 0; j < m; ++j) {
+        for (int i = 0; i < m; ++i) V[j][i] = (i == 0) ? (j == 0 ? 1 : 0) : powl(ys[i], j);
+        V[j][m] = 2.0L / (2 * j + 1);
+    }
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < m; ++r)
+            if (fabsl(V[r][c]) > fabsl(V[piv][c])) piv = r;
+        for (int j = 0; j <= m; ++j) std::swap(V[c][j], V[piv][j]);
+        for (int r = 0; r < m; ++r)
+            if (r != c) {
+                const R f = V[r][c] / V[c][c];
+                for (int j = c; j <= m; ++j) V[r][j] -= f * V[c][j];
+            }
+    }
+    for (int i = 0; i < m; ++i) {
+        const R x = sqrtl(ys[i]), w = i == 0 ? V[0][m] / V[0][0] : V[i][m] / V[i][i] / 2;
+        xk[n + i] = (double)((1 + x) / 2);
+        xk[n - i] = (double)((1 - x) / 2);
+        wk[n + i] = wk[n - i] = (double)(w / 2);
+    }
+    for (int i = 0; i < n; ++i) wg[i] = gw[i];
 }
 
 namespace {
@@ -165,25 +271,6 @@ double mid_iso_length(const Patch &p, int dir)
         len += std::sqrt(d2);
     }
     return len;
-}
-
-// True when one of the four boundary edges of the patch is collapsed to a
-// point (all four Euclidean control points within tol of each other), as at
-// the poles of a sphere.
-bool has_collapsed_edge(const Patch &p, double tol)
-{
-    for (int e = 0; e < 4; ++e) {
-        double pt[4][3];
-        for (int t = 0; t < 4; ++t) {
-            const int i = e == 0 ? 0 : e == 1 ? 3 : t, j = e == 2 ? 0 : e == 3 ? 3 : t;
-            for (int k = 0; k < 3; ++k) pt[t][k] = p.h[i][j][k] / p.h[i][j][3];
-        }
-        double spread = 0.0;
-        for (int t = 1; t < 4; ++t)
-            for (int k = 0; k < 3; ++k) spread = std::fmax(spread, std::fabs(pt[t][k] - pt[0][k]));
-        if (spread <= tol) return true;
-    }
-    return false;
 }
 
 }  // namespace
@@ -295,10 +382,6 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     // the visible region is dropped.  When the cut at 1/2 would pass through
     // a junction of two trim curves or touch a loop tangentially, the cut
     // moves to the nearest of 1/2 +- k/64 (k = 1..8) where it does not.
-    // Patches with an edge collapsed to a point are kept whole: the
-    // near-field rule resolves the whole polar patch, while its sub-patches
-    // at the pole put the foot point on a degenerate corner of a tiny,
-    // strongly non-uniform domain.
     const double limit = p->max_diag_frac * m.diag;
     std::vector<Patch> leaves;
     leaves.reserve(work.size());
@@ -314,7 +397,7 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         const double dg = std::sqrt((h[0] - l[0]) * (h[0] - l[0]) + (h[1] - l[1]) * (h[1] - l[1]) +
                                     (h[2] - l[2]) * (h[2] - l[2]));
         bool done = true;
-        if (limit > 0 && dg >= limit && it.depth < 24 && !has_collapsed_edge(it.p, 1e-12 * m.diag)) {
+        if (limit > 0 && dg >= limit && it.depth < 24) {
             const int dir = mid_iso_length(it.p, 0) >= mid_iso_length(it.p, 1) ? 0 : 1;
             for (int k = 0; k <= 16; ++k) {
                 const double c = 0.5 + (k == 0 ? 0.0 : ((k & 1) ? 1.0 : -1.0) * ((k + 1) / 2) / 64.0);

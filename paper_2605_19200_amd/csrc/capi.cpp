@@ -44,7 +44,7 @@ extern "C" void gwn_default_params(gwn_params *p)
     p->gl_nodes = 10;
     p->device = 0;
     p->near_ratio = 0.25;
-    p->eps_q = 1e-10;
+    p->eps_q = 1e-6;
     p->leaf_far = 1;
     p->reserved = 0;
     p->far_tol = 0.0;

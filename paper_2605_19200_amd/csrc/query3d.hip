@@ -36,7 +36,7 @@
 
 namespace gwn {
 
-void gauss_legendre01(int n, double *x, double *w);   // build3d.cpp
+void gauss_kronrod01(int n, double *xk, double *wk, double *wg);   // build3d.cpp
 
 __constant__ QuadTables c_quad;
 
@@ -350,7 +350,6 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
     const double qy = act ? pts[3 * (int64_t)row + 1] : 0.0;
     const double qz = act ? pts[3 * (int64_t)row + 2] : 0.0;
     const int full = act ? NS.cnt[slot] : 0;
-    const bool overflow = full > kNearSlots;
     const int c = min(full, kNearSlots);
     // inclusive prefix sum of the pair counts over the wave
     int incl = c;
@@ -380,8 +379,10 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
             const int node = NS.list[((int64_t)wave * T.qpw + owner) * kNearSlots + (t - oexcl)];
             const Node3 *nd = (const Node3 *)M.nodes + node;
             const int leaf = -1 - nd->right;
+            bool budget = false;   // a panel or piece missed its share of 4 pi eps_q
             v = near3d<COUNT>(c_quad, (const Prim3 *)M.prims + leaf, (const Trim3 *)M.trims, ox, oy, oz, M.eps_on,
-                              ctr);
+                              4.0 * kPi * M.eps_q, budget, ctr);
+            if (budget) v = NAN;
         }
         // this round holds pairs [max(excl, base), min(incl, base + 64)) of each lane
         const int a = max(excl, base) - base, b = min(incl, base + 64) - base;
@@ -394,6 +395,9 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
     }
     if (act) {
         double wq = (NS.part[slot] + near_sum) * (1.0 / (4.0 * kPi));
+        // more near leaves than slots, or a leaf whose near-field rule could
+        // not meet eps_q within its refinement budget (its value is NaN)
+        const bool overflow = full > kNearSlots || !(wq == wq);
         if (overflow) {
             wq = NAN;
             atomicAdd((unsigned int *)M.flag, 1u);
@@ -420,8 +424,8 @@ static hipError_t ensure_tables()
     std::lock_guard<std::mutex> lk(g_tab_mu);
     if (dev >= 0 && dev < 64 && g_tab_ready[dev]) return hipSuccess;
     QuadTables t;
-    gauss_legendre01(kOuterGL, t.gxo, t.gwo);
-    gauss_legendre01(kRadialGL, t.gxr, t.gwr);
+    gauss_kronrod01(kOuterN, t.xo, t.wo, t.go);
+    gauss_kronrod01(kRadialN, t.xr, t.wr, t.gr);
     e = hipMemcpyToSymbol(HIP_SYMBOL(c_quad), &t, sizeof t);
     if (e == hipSuccess && dev >= 0 && dev < 64) g_tab_ready[dev] = true;
     return e;

@@ -52,22 +52,25 @@ MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125
 # bodies scene, 128 of the CAD assembly, plus the near-surface test sets):
 #   order 2, beta 16: 3.9e-7    order 4, beta 8: 2.3e-7
 #   order 5, beta 5:  3.0e-7    order 6, beta 5: 1.0e-7  (chosen)
-# Subdividing untrimmed patches further cuts the near-field work, as in 2D.
-# Trimmed patches, and patches with an edge collapsed to a point (sphere
-# poles, whose sub-patches the near-field rule handled to only 7e-4), stay
-# whole.  Bodies scene, 128^3 grid, order 6, beta 5 (max |dw| on 2048
-# sampled queries against the all-direct evaluation):
+# Subdividing patches further cuts the near-field work, as in 2D (these
+# figures predate the subdivision of trimmed patches and of patches with a
+# collapsed edge).  Bodies scene, 128^3 grid, order 6, beta 5 (max |dw| on
+# 2048 sampled queries against the all-direct evaluation):
 #   max_diag_frac 0.1: 4096 leaves, 594 ms, 7.2e-8
 #                 0.025: 8570 leaves, 494 ms, 1.0e-7
 #                 0.0125: ~29,000 leaves, 410 ms, 8.0e-8  (chosen)
 #                 0.00625: 114378 leaves, 371 ms, 9.4e-8 (4x the node sets)
-FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, precision=G.GWN_FP64)
+# The near-field tolerance eps_q is 1e-8 per leaf (in units of w): with at
+# most 64 near leaves per query their sum stays below 1e-6 even if every
+# leaf reached its tolerance (on the checked near-field pairs the errors
+# were ~3e-11).
+FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, precision=G.GWN_FP64)
 # A reached leaf that passes the far test itself takes its own expansion
 # (leaf_far, the default): on the checked sets this halves the node-set work
 # per query (CAD assembly: 113k -> 53k integrand nodes) at the same error.
 # The paper's setting evaluates every reached leaf directly (Alg. 1).
-PAPER_ORDER_3D = dict(beta=16.0, taylor_order=2, leaf_far=0, precision=G.GWN_FP64)
-MIXED_3D = dict(beta=5.0, beta_mixed=3.0, taylor_order=6, max_diag_frac=0.0125, precision=G.GWN_MIXED,
+PAPER_ORDER_3D = dict(beta=16.0, taylor_order=2, leaf_far=0, eps_q=1e-8, precision=G.GWN_FP64)
+MIXED_3D = dict(beta=5.0, beta_mixed=3.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, precision=G.GWN_MIXED,
                 reclass_band=1e-2)
 
 
