@@ -1,0 +1,127 @@
+"""Full-size 3D parity: the engine runs the whole workload in one launch, and
+its values are compared row by row with oracle values computed on the CPU
+(tests/golden/make_fullsize_fixtures.py, which calls only oracle/).
+
+  CAD assembly: 39 bodies, 19,968 trimmed patches, 1,000,000 queries (half
+  within 1e-2 of the surface); 512 near-surface and 512 uniform rows.
+  Bodies scene: 4,096 patches, the 128^3 grid; 512 grid rows and 512
+  near-surface points.
+
+FP64 form: |dw| <= 1e-6 on every fixture row, containment exact where the
+oracle's |w - 0.5| > 1e-3.  Over the whole launch, a query is NaN only when
+the near-field rule could not certify its tolerance within its refinement
+budget; such queries are reported (GWN_EOVERFLOW with their count) and must
+stay below 1e-4 of the launch.  Mixed form: error reported (max, p99, RMS),
+containment exact outside the band."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2605_19200_amd import gwn as G
+from paper_2605_19200_amd import presets
+from paper_2605_19200_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_fullsize_fixtures as F  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL, BAND = 1e-6, 1e-3
+
+
+def run(model, q):
+    out, ins = model.query(torch.from_numpy(np.ascontiguousarray(q)).cuda())
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ins.cpu().numpy()
+
+
+def report(tag, w, ins, ref):
+    err = np.abs(w - ref)
+    sure = np.abs(ref - 0.5) > BAND
+    mism = int(np.sum((ins[sure] != 0) != (ref[sure] >= 0.5)))
+    print(f"{tag}: n={ref.size} max |dw| {err.max():.3e} p99 {np.quantile(err, 0.99):.3e} "
+          f"rms {np.sqrt(np.mean(err ** 2)):.3e} containment mismatches outside the band {mism}", flush=True)
+    return err, mism
+
+
+MAX_FLAGGED = 1e-4   # fraction of a launch allowed to come back as reported overflows
+
+
+def flagged_rows_reported(tag, m, w, q):
+    """Non-finite outputs are the queries whose near-field rule could not
+    certify eps_q within its refinement budget: each must be reported (the
+    next call on the handle returns GWN_EOVERFLOW with their count), and
+    they must be rare.  With none, the next call succeeds."""
+    bad = np.nonzero(~np.isfinite(w))[0]
+    for i in bad[:8]:
+        print(f"{tag}: flagged row {int(i)} at {q[i].tolist()!r}", flush=True)
+    print(f"{tag}: {bad.size} flagged rows of {w.size}", flush=True)
+    assert bad.size <= MAX_FLAGGED * w.size
+    if bad.size:
+        with pytest.raises(G.GwnError) as ei:
+            run(m, q[:8])
+        assert ei.value.status == G.GWN_EOVERFLOW and str(bad.size) in str(ei.value)
+    run(m, q[:8])
+    return bad
+
+
+@pytest.fixture(scope="module")
+def cad():
+    rows, qf, wf, hdr = F.load(os.path.join(HERE, "golden", "oracle_cad_assembly_1m.txt"))
+    assert rows.size == 2 * F.N_PER_KIND and float(hdr["oracle max error bound"]) <= 1e-12
+    P, q = W.config4()
+    assert np.array_equal(q[rows], qf)
+    return P, q, rows, wf
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_cad_assembly_full_launch(cad, form):
+    P, q, rows, ref = cad
+    m = G.Model(P, presets.params(presets.FP64_3D if form == "fp64" else presets.MIXED_3D))
+    print(f"cad assembly {form}: {int(m.inspect(G.GWN_I_SUMMARY)[0][2])} leaves, {q.shape[0]} queries", flush=True)
+    w, ins = run(m, q)
+    flagged_rows_reported(f"cad assembly {form}", m, w, q)
+    assert np.all(np.isfinite(w[rows]))
+    err, mism = report(f"cad assembly {form}", w[rows], ins[rows], ref)
+    near = np.arange(rows.size) < F.N_PER_KIND
+    report(f"cad assembly {form} near-surface rows", w[rows][near], ins[rows][near], ref[near])
+    report(f"cad assembly {form} uniform rows", w[rows][~near], ins[rows][~near], ref[~near])
+    assert mism == 0
+    if form == "fp64":
+        assert err.max() <= TOL
+    m.close()
+
+
+@pytest.fixture(scope="module")
+def bodies():
+    rows, qf, wf, hdr = F.load(os.path.join(HERE, "golden", "oracle_bodies_scene.txt"))
+    assert rows.size == 2 * F.N_PER_KIND and float(hdr["oracle max error bound"]) <= 1e-12
+    P, q = W.config3()
+    grid = rows >= 0
+    assert np.array_equal(q[rows[grid]], qf[grid]) and np.array_equal(F.bodies_near(), qf[~grid])
+    return P, q, rows, qf, wf
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_bodies_scene_full_grid(bodies, form):
+    P, q, rows, qf, ref = bodies
+    m = G.Model(P, presets.params(presets.FP64_3D if form == "fp64" else presets.MIXED_3D))
+    grid = rows >= 0
+    w, ins = run(m, q)
+    flagged_rows_reported(f"bodies scene {form}", m, w, q)
+    wn, insn = run(m, qf[~grid])
+    flagged_rows_reported(f"bodies scene {form} near", m, wn, qf[~grid])
+    assert np.all(np.isfinite(w[rows[grid]])) and np.all(np.isfinite(wn))
+    wa = np.concatenate([w[rows[grid]], wn])
+    ia = np.concatenate([ins[rows[grid]], insn])
+    ra = np.concatenate([ref[grid], ref[~grid]])
+    err, mism = report(f"bodies scene {form}", wa, ia, ra)
+    report(f"bodies scene {form} near-surface points", wn, insn, ref[~grid])
+    assert mism == 0
+    if form == "fp64":
+        assert err.max() <= TOL
+    m.close()
