@@ -207,101 +207,72 @@ GWN_HD inline Curve2 square_edge(int e)
     return c;
 }
 
-// H(p) = integral_0^1 g(c + tau (p - c)) tau dtau, sinh-graded at tau = 0,
-// to the absolute tolerance tolH (err: its estimate; ovf set when a piece
-// misses its share at the last refinement level).
-template <class CtrT>
-GWN_HD inline double radial(const QuadTables &Q, const double *__restrict__ h, double cu, double cv, double ru,
-                            double rv, double qx, double qy, double qz, double dist, const double Su[3],
-                            const double Sv[3], double tolH, double qnorm, Budget &B, double &err, double &rnd_out,
-                            bool &ovf, CtrT &ctr, bool count)
+// ---------------------------------------------------------------------------
+// Cross-lane operations.  The rule below runs one (query, leaf) pair per
+// wave of 64 lanes: every value that steers it (foot point, panels,
+// refinement levels, budget) is the same on all lanes, and the lanes share
+// out the integrand evaluations.  Every call of these operations is made by
+// all 64 lanes at the same point of the rule.  DevWave maps them to the
+// wave's cross-lane instructions; `bcast` takes a source lane that is the
+// same on all lanes.
+// ---------------------------------------------------------------------------
+struct DevWave {
+    __device__ int lane() const { return __lane_id(); }
+    __device__ double shfl(double x, int src) const { return __shfl(x, src); }
+    __device__ int shfl(int x, int src) const { return __shfl(x, src); }
+    __device__ double shfl_xor(double x, int m) const { return __shfl_xor(x, m); }
+    __device__ int shfl_xor(int x, int m) const { return __shfl_xor(x, m); }
+    __device__ double bcast(double x, int src) const
+    {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+    __device__ int bcast(int x, int src) const { return __builtin_amdgcn_readlane(x, src); }
+    __device__ unsigned long long ballot(bool p) const { return __ballot(p); }
+};
+
+// Sum over the caller's group of 16 lanes (a butterfly: every lane of the
+// group gets the same bits).
+template <class Wv>
+GWN_HD inline double sum16(const Wv &wv, double x)
 {
-    const double lx = Su[0] * ru + Sv[0] * rv, ly = Su[1] * ru + Sv[1] * rv, lz = Su[2] * ru + Sv[2] * rv;
-    const double L = sqrt(lx * lx + ly * ly + lz * lz);
-    const double eps = L > 0.0 ? dist / L : 1.0;
-    // eps >= 0.5: two uniform pieces in tau.  Otherwise pieces in sigma with
-    // tau = eps sinh(mu sigma): tau <= 4 eps, 4 eps <= tau <= 0.1,
-    // tau >= 0.1 (fewer when eps is not small; no piece may reach past
-    // tau = 1, where the patch is evaluated outside its parameter square).
-    // One node loop, so the patch evaluation is inlined once.
-    const bool uni = eps >= 0.5;
-    double mu = 1.0, cuts[4] = {0.0, 0.5, 1.0, 1.0};
-    int npieces = 2;
-    if (!uni) {
-        mu = asinh(1.0 / eps);
-        const double sa = asinh(4.0) / mu, sb = asinh(0.1 / eps) / mu;
-        npieces = 1;
-        cuts[1] = 1.0;
-        cuts[2] = 1.0;
-        if (sb > sa) { cuts[1] = sa; cuts[2] = sb; npieces = 3; }
-        else if (sa < 1.0) { cuts[1] = sa; npieces = 2; }
-    }
-    const double tol_piece = tolH / npieces;
-    double sum = 0.0, esum = 0.0, rsum = 0.0;
-    long long evals = 0;
-#pragma unroll 1
-    for (int piece = 0; piece < npieces; ++piece) {
-        const double a = cuts[piece], b = cuts[piece + 1];
-        double val = 0.0, e = 0.0, rnd = 0.0;
-#pragma unroll 1
-        for (int level = 0; level <= kRadialLevels; ++level) {
-            const int nsub = 1 << level;
-            const double w = (b - a) / nsub;
-            rnd = 0.0;
-            val = 0.0;
-            e = 0.0;
-#pragma unroll 1
-            for (int sp = 0; sp < nsub; ++sp) {
-                const double pa = a + sp * w, pw = w;
-                double K = 0.0, G = 0.0, fabs_sum = 0.0, noise = 0.0;
-                double fv[kGKr];
-#pragma unroll 1
-                for (int i = 0; i < kGKr; ++i) {
-                    const double x = pa + pw * Q.xr[i];
-                    double tau, jac;
-                    if (uni) {
-                        tau = x;
-                        jac = 1.0;
-                    } else {
-                        // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
-                        const double em = expm1(mu * x), ie = 1.0 / (1.0 + em);
-                        tau = eps * 0.5 * (em + em * ie);
-                        jac = eps * mu * 0.5 * (1.0 + em + ie);
-                    }
-                    HomEval ev;
-                    hom_eval(h, cu + tau * ru, cv + tau * rv, qx, qy, qz, ev);
-                    const double f = jac * tau * density(ev);
-                    const double a2 = ev.A[0] * ev.A[0] + ev.A[1] * ev.A[1] + ev.A[2] * ev.A[2];
-                    fv[i] = f;
-                    K += Q.wr[i] * f;
-                    fabs_sum += Q.wr[i] * fabs(f);
-                    noise += Q.wr[i] * fabs(f) * (1.0 + (a2 > 0.0 ? qnorm * fabs(ev.W) / sqrt(a2) : 0.0));
-                }
-#pragma unroll
-                for (int i = 0; i < kRadialN; ++i) G += Q.gr[i] * fv[2 * i + 1];
-                double asc = 0.0;
-#pragma unroll
-                for (int i = 0; i < kGKr; ++i) asc += Q.wr[i] * fabs(fv[i] - K);
-                val += pw * K;
-                e += gk_error(pw * K, pw * G, pw * asc);
-                rnd += gk_round(pw * noise);
-                evals += kGKr;
-            }
-            if (e <= fmax(tol_piece, rnd)) break;
-            if (level == kRadialLevels || B.spent + evals > kMaxEvalsPerPair) {
-                ovf = true;
-                break;
-            }
+    x += wv.shfl_xor(x, 8);
+    x += wv.shfl_xor(x, 4);
+    x += wv.shfl_xor(x, 2);
+    x += wv.shfl_xor(x, 1);
+    return x;
+}
+
+// Minimum of d over the wave and its index k (the smaller k on ties).
+template <class Wv>
+GWN_HD inline void argmin64(const Wv &wv, double &d, int &k)
+{
+    for (int m = 32; m > 0; m >>= 1) {
+        const double od = wv.shfl_xor(d, m);
+        const int ok = wv.shfl_xor(k, m);
+        if (od < d || (od == d && ok < k)) {
+            d = od;
+            k = ok;
         }
-        sum += val;
-        esum += e;
-        rsum += rnd;
     }
-    if (count) ctr_add(ctr, GWN_C_PIECES, evals);
-    B.spent += evals;
-    err = esum;
-    rnd_out = rsum;
-    return sum;
+}
+
+GWN_HD inline int imin(int a, int b) { return a < b ? a : b; }
+
+// Position of the k-th set bit (from 0) of m, which has more than k bits.
+GWN_HD inline int kth_bit(unsigned long long m, int k)
+{
+    int pos = 0;
+    for (int w = 32; w > 0; w >>= 1) {
+        const int c = __builtin_popcountll((m >> pos) & ((1ull << w) - 1));
+        if (c <= k) {
+            k -= c;
+            pos += w;
+        }
+    }
+    return pos;
 }
 
 // Geometric panels on [a, b] graded from `c` (in [a, b]) with first width
@@ -324,19 +295,178 @@ GWN_HD inline int count_panels(double a, double b, double c, double h0)
     return n;
 }
 
-// The same panels, each integrated to its share of the leaf's budget B:
-// f(t, tol_f, err_f, rnd_f) returns the integrand at t, which carries its
-// own error estimate err_f (computed against tol_f) and rounding level rnd_f.
-// A panel whose estimate exceeds its share is integrated again as 2, 4, ...
-// equal sub-panels.
-template <class F>
-GWN_HD inline double graded_panels(const QuadTables &Q, double a, double b, double c, double h0, Budget &B,
-                                   bool &ovf, F &&f)
+struct NearFrame {
+    double cu, cv;       // foot point
+    double dist;         // distance from q to the surface (1e300 when on it)
+    double dparam;       // grading width near c, in parameter units
+    double Su[3], Sv[3]; // partials at c
+    double ew_u, ew_v;   // weak metric direction
+    double anis;         // sqrt(l1 / l2)
+};
+
+// Sub-panels of an outer panel whose nodes are integrated together: 9 nodes
+// each, three radial pieces per node, one task lane per piece.
+constexpr int kSubPerChunk = 2;
+
+// Values of the outer integrand at the Kronrod nodes of the sub-panels
+// sp0 .. sp0 + nc - 1 of width sw of the panel starting at pa: lane m < 9 nc
+// gets node m % 9 of sub-panel sp0 + m / 9, f = cross(gamma - c, gamma') H
+// with its error estimate ef and rounding level rf, where H(p) =
+// integral_0^1 g(c + tau (p - c)) tau dtau is sinh-graded at tau = 0 and
+// taken to the tolerance tol_f / |cross|.
+// H comes in up to three pieces (tau <= 4 eps, 4 eps <= tau <= 0.1, tau >=
+// 0.1 with eps = d / |J (p - c)|; two uniform pieces when eps >= 0.5; no
+// piece reaches past tau = 1), each the task of lane 3 m + p: integrated
+// by the 13-point Kronrod rule on 1, 2, 4, ... 2^kRadialLevels equal parts
+// until its estimate meets its share.  The parts of the pending tasks are
+// shared out over the wave's four groups of 16 lanes, one part (13 nodes)
+// per group and round; each task adds the sums of its parts in their order.
+template <class Wv, class CtrT>
+GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double *__restrict__ h, const Curve2 &cv,
+                                const NearFrame &fr, double qx, double qy, double qz, double qnorm, double pa,
+                                double sw, int sp0, int nc, double tol_f, Budget &B, bool &ovf, CtrT &ctr, bool count,
+                                double &f, double &ef, double &rf)
+{
+    const int ln = wv.lane();
+    const int M = kGKo * nc;
+    const int m = ln / 3, p = ln - 3 * (ln / 3);
+    const bool has = m < M;
+    const int mj = has ? m / kGKo : 0, mi = has ? m - kGKo * (m / kGKo) : 0;
+    const double sa = pa + (sp0 + mj) * sw;
+    double pu, pv, pdu, pdv;
+    curve_eval(cv, sa + sw * Q.xo[mi], pu, pv, pdu, pdv);
+    const double ru = pu - fr.cu, rv = pv - fr.cv;
+    const double cr = ru * pdv - rv * pdu;
+    const double lx = fr.Su[0] * ru + fr.Sv[0] * rv, ly = fr.Su[1] * ru + fr.Sv[1] * rv,
+                 lz = fr.Su[2] * ru + fr.Sv[2] * rv;
+    const double L = sqrt(lx * lx + ly * ly + lz * lz);
+    const double eps = L > 0.0 ? fr.dist / L : 1.0;
+    const bool uni = eps >= 0.5;
+    double mu = 1.0, cuts[4] = {0.0, 0.5, 1.0, 1.0};
+    int np = 2;
+    if (!uni) {
+        mu = asinh(1.0 / eps);
+        const double s4 = asinh(4.0) / mu, s01 = asinh(0.1 / eps) / mu;
+        np = 1;
+        cuts[1] = 1.0;
+        cuts[2] = 1.0;
+        if (s01 > s4) { cuts[1] = s4; cuts[2] = s01; np = 3; }
+        else if (s4 < 1.0) { cuts[1] = s4; np = 2; }
+    }
+    const double tol_piece = tol_f / fabs(cr) / np;
+    const double a = cuts[p], b = cuts[p + 1];
+    double tval = 0.0, te = 0.0, trnd = 0.0;
+    bool tovf = false;
+    unsigned long long pend = wv.ballot(has && cr != 0.0 && p < np);
+    long long evals = 0;
+    const int g = ln >> 4, i = ln & 15;
+#pragma unroll 1
+    for (int l = 0; l <= kRadialLevels && pend; ++l) {
+        const int nsub = 1 << l;
+        const int nra = __builtin_popcountll(pend) << l;
+        if ((pend >> ln) & 1) {
+            tval = 0.0;
+            te = 0.0;
+            trnd = 0.0;
+        }
+#pragma unroll 1
+        for (int r0 = 0; r0 < nra; r0 += 4) {
+            const int ra = r0 + g;
+            const bool vra = ra < nra;
+            const int task = vra ? kth_bit(pend, ra >> l) : 0;
+            const double ta = wv.shfl(a, task), tb = wv.shfl(b, task);
+            const double tru = wv.shfl(ru, task), trv = wv.shfl(rv, task);
+            const double teps = wv.shfl(eps, task), tmu = wv.shfl(mu, task);
+            const int tuni = wv.shfl((int)uni, task);
+            const double w = (tb - ta) / nsub;
+            const double xa = ta + (ra & (nsub - 1)) * w;
+            const bool node = vra && i < kGKr;
+            double fx = 0.0, nz = 0.0;
+            if (node) {
+                const double x = xa + w * Q.xr[i];
+                double tau, jac;
+                if (tuni) {
+                    tau = x;
+                    jac = 1.0;
+                } else {
+                    // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
+                    const double em = expm1(tmu * x), ie = 1.0 / (1.0 + em);
+                    tau = teps * 0.5 * (em + em * ie);
+                    jac = teps * tmu * 0.5 * (1.0 + em + ie);
+                }
+                HomEval ev;
+                hom_eval(h, fr.cu + tau * tru, fr.cv + tau * trv, qx, qy, qz, ev);
+                fx = jac * tau * density(ev);
+                const double a2 = ev.A[0] * ev.A[0] + ev.A[1] * ev.A[1] + ev.A[2] * ev.A[2];
+                nz = fabs(fx) * (1.0 + (a2 > 0.0 ? qnorm * fabs(ev.W) / sqrt(a2) : 0.0));
+            }
+            const double wk = node ? Q.wr[i] : 0.0;
+            const double wg = node && (i & 1) ? Q.gr[i >> 1] : 0.0;
+            const double K = sum16(wv, wk * fx);
+            const double G = sum16(wv, wg * fx);
+            const double asc = sum16(wv, wk * fabs(fx - K));
+            const double noise = sum16(wv, wk * nz);
+            const double pval = w * K, perr = gk_error(w * K, w * G, w * asc), prnd = gk_round(w * noise);
+#pragma unroll 1
+            for (int gg = 0; gg < 4 && r0 + gg < nra; ++gg) {
+                const int tk = wv.bcast(task, 16 * gg);
+                const double v1 = wv.bcast(pval, 16 * gg), e1 = wv.bcast(perr, 16 * gg), r1 = wv.bcast(prnd, 16 * gg);
+                if (ln == tk) {
+                    tval += v1;
+                    te += e1;
+                    trnd += r1;
+                }
+            }
+        }
+        evals += (long long)nra * kGKr;
+        B.spent += (long long)nra * kGKr;
+        bool again = false;
+        if (((pend >> ln) & 1) && !(te <= fmax(tol_piece, trnd))) {
+            if (l == kRadialLevels || B.spent > kMaxEvalsPerPair) tovf = true;
+            else again = true;
+        }
+        pend = wv.ballot(again);
+    }
+    if (wv.ballot(tovf)) ovf = true;
+    if (count && ln == 0) ctr_add(ctr, GWN_C_PIECES, evals);
+    // node m (lane m) adds its pieces in order
+    double H = 0.0, eH = 0.0, rH = 0.0;
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp) {
+        const int src = imin(3 * ln + pp, 63);
+        const double v1 = wv.shfl(tval, src), e1 = wv.shfl(te, src), r1 = wv.shfl(trnd, src);
+        if (pp < wv.shfl(np, src)) {
+            H += v1;
+            eH += e1;
+            rH += r1;
+        }
+    }
+    const double crm = wv.shfl(cr, imin(3 * ln, 63));
+    f = 0.0;
+    ef = 0.0;
+    rf = 0.0;
+    if (ln < M && crm != 0.0) {
+        f = crm * H;
+        ef = fabs(crm) * eH;
+        rf = fabs(crm) * rH;
+    }
+}
+
+// The graded panels of one boundary curve on [a, b] (from `c`, first width
+// h0), each integrated to its share of the leaf's budget B: a panel whose
+// estimate -- its Kronrod estimate plus the radial estimates of its nodes --
+// exceeds its share is integrated again as 2, 4, ... equal sub-panels.
+template <class Wv, class CtrT>
+GWN_HD inline double graded_panels(const Wv &wv, const QuadTables &Q, const double *__restrict__ h, const Curve2 &cv,
+                                   const NearFrame &fr, double qx, double qy, double qz, double qnorm, double a,
+                                   double b, double c, double h0, Budget &B, bool &ovf, CtrT &ctr, bool count)
 {
     double total = 0.0;
+#pragma unroll 1
     for (int side = 0; side < 2; ++side) {
         const double end = side == 0 ? b : a;
         double lo = c, w = h0;
+#pragma unroll 1
         for (int k = 0; k < kMaxPanelsSide; ++k) {
             if (side == 0 ? lo >= end : lo <= end) break;
             double hi = side == 0 ? fmin(end, lo + w) : fmax(end, lo - w);
@@ -352,30 +482,35 @@ GWN_HD inline double graded_panels(const QuadTables &Q, double a, double b, doub
                 e = 0.0;
                 val = 0.0;
 #pragma unroll 1
-                for (int sp = 0; sp < nsub; ++sp) {
-                    const double sa = pa + sp * sw;
-                    double K = 0.0, G = 0.0, fabs_sum = 0.0, erad = 0.0, rrad = 0.0;
-                    double fv[kGKo];
+                for (int sp0 = 0; sp0 < nsub; sp0 += kSubPerChunk) {
+                    const int nc = imin(kSubPerChunk, nsub - sp0);
+                    double f, ef, rf;
+                    // the radial part of the estimate stays within half the
+                    // share
+                    outer_values(wv, Q, h, cv, fr, qx, qy, qz, qnorm, pa, sw, sp0, nc, 0.5 * share / len, B, ovf, ctr,
+                                 count, f, ef, rf);
 #pragma unroll 1
-                    for (int i = 0; i < kGKo; ++i) {
-                        // the radial part of the estimate stays within half
-                        // the share
-                        double ef = 0.0, rf = 0.0;
-                        const double fx = f(sa + sw * Q.xo[i], 0.5 * share / len, ef, rf);
-                        fv[i] = fx;
-                        K += Q.wo[i] * fx;
-                        fabs_sum += Q.wo[i] * fabs(fx);
-                        erad += Q.wo[i] * ef;
-                        rrad += Q.wo[i] * rf;
+                    for (int j = 0; j < nc; ++j) {
+                        double K = 0.0, G = 0.0, fabs_sum = 0.0, erad = 0.0, rrad = 0.0;
+                        double fv[kGKo];
+#pragma unroll
+                        for (int i = 0; i < kGKo; ++i) {
+                            const double fx = wv.bcast(f, kGKo * j + i);
+                            fv[i] = fx;
+                            K += Q.wo[i] * fx;
+                            fabs_sum += Q.wo[i] * fabs(fx);
+                            erad += Q.wo[i] * wv.bcast(ef, kGKo * j + i);
+                            rrad += Q.wo[i] * wv.bcast(rf, kGKo * j + i);
+                        }
+#pragma unroll
+                        for (int i = 0; i < kOuterN; ++i) G += Q.go[i] * fv[2 * i + 1];
+                        double asc = 0.0;
+#pragma unroll
+                        for (int i = 0; i < kGKo; ++i) asc += Q.wo[i] * fabs(fv[i] - K);
+                        val += sw * K;
+                        e += gk_error(sw * K, sw * G, sw * asc) + sw * erad;
+                        rnd += gk_round(sw * fabs_sum) + sw * rrad;
                     }
-#pragma unroll
-                    for (int i = 0; i < kOuterN; ++i) G += Q.go[i] * fv[2 * i + 1];
-                    double asc = 0.0;
-#pragma unroll
-                    for (int i = 0; i < kGKo; ++i) asc += Q.wo[i] * fabs(fv[i] - K);
-                    val += sw * K;
-                    e += gk_error(sw * K, sw * G, sw * asc) + sw * erad;
-                    rnd += gk_round(sw * fabs_sum) + sw * rrad;
                 }
                 if (e <= fmax(share, rnd)) break;
                 if (level == kOuterLevels || B.spent > kMaxEvalsPerPair) {
@@ -393,52 +528,66 @@ GWN_HD inline double graded_panels(const QuadTables &Q, double a, double b, doub
     return total;
 }
 
-struct NearFrame {
-    double cu, cv;       // foot point
-    double dist;         // distance from q to the surface (1e300 when on it)
-    double dparam;       // grading width near c, in parameter units
-    double Su[3], Sv[3]; // partials at c
-    double ew_u, ew_v;   // weak metric direction
-    double anis;         // sqrt(l1 / l2)
-};
+// Grading centres of one boundary curve, each with the width of its first
+// panel: the point of the curve nearest c, and, for a strongly anisotropic
+// metric at c, the crossings of the ray from c along the weak direction;
+// sorted, and merged where they lie within each other's first panel.
+// 17 samples of the curve locate them; 64-point multisection refines them
+// (kMultisect rounds for a crossing, kMultimin for the nearest point).
+constexpr int kMultisect = 8;   // width (1/16) / 65^8 ~ 2e-16
+constexpr int kMultimin = 6;    // width (1/8) / 31.5^6 ~ 1e-10
 
-// Outer integral over one boundary curve, panels graded from the point
-// nearest c and from the crossings of the ray from c along the weak
-// direction.
-template <class CtrT>
-GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__restrict__ h, const Curve2 &cv,
-                                        const NearFrame &fr, double qx, double qy, double qz, bool count_only,
-                                        Budget &B, bool &ovf, CtrT &ctr, bool count)
+template <class Wv>
+GWN_HD inline int curve_centres(const Wv &wv, const Curve2 &cv, const NearFrame &fr, double centres[3],
+                                double widths[3])
 {
-    double centres[3], widths[3];
+    const int ln = wv.lane();
     int nc = 0;
-    int best = 0;
-    double bd = INFINITY, prev = 0.0;
-    for (int k = 0; k <= 16; ++k) {
-        const double t = k / 16.0;
+    double d2 = INFINITY, sd;
+    {
+        const int k = ln < 16 ? ln : 16;
         double u, v, du, dv;
-        curve_eval(cv, t, u, v, du, dv);
-        const double d2 = (u - fr.cu) * (u - fr.cu) + (v - fr.cv) * (v - fr.cv);
-        if (d2 < bd) { bd = d2; best = k; }
-        const double sd = (u - fr.cu) * fr.ew_v - (v - fr.cv) * fr.ew_u;
-        if (fr.anis < 0.5 && k > 0 && nc < 2 && ((prev < 0.0 && sd >= 0.0) || (prev > 0.0 && sd <= 0.0))) {
-            double lo = (k - 1) / 16.0, hi = t, flo = prev;
-            for (int it = 0; it < 50; ++it) {
-                const double m = 0.5 * (lo + hi);
-                double mu, mv, mdu, mdv;
-                curve_eval(cv, m, mu, mv, mdu, mdv);
-                const double fm = (mu - fr.cu) * fr.ew_v - (mv - fr.cv) * fr.ew_u;
-                if ((flo < 0.0) == (fm < 0.0)) { lo = m; flo = fm; } else hi = m;
-            }
-            const double tr = 0.5 * (lo + hi);
-            double ru, rv, rdu, rdv;
-            curve_eval(cv, tr, ru, rv, rdu, rdv);
-            const double rr = sqrt((ru - fr.cu) * (ru - fr.cu) + (rv - fr.cv) * (rv - fr.cv));
-            const double speed = sqrt(rdu * rdu + rdv * rdv);
-            centres[nc] = tr;
-            widths[nc++] = speed > 0.0 ? fmax(fr.anis * rr, fr.dparam) / speed : 1.0;
+        curve_eval(cv, k / 16.0, u, v, du, dv);
+        if (ln <= 16) d2 = (u - fr.cu) * (u - fr.cu) + (v - fr.cv) * (v - fr.cv);
+        if (!(d2 < INFINITY)) d2 = INFINITY;
+        sd = (u - fr.cu) * fr.ew_v - (v - fr.cv) * fr.ew_u;
+    }
+    int best = ln;
+    {
+        double bd = d2;
+        argmin64(wv, bd, best);
+    }
+    const double prev = wv.shfl(sd, ln > 0 ? ln - 1 : 0);
+    unsigned long long cm = wv.ballot(fr.anis < 0.5 && ln >= 1 && ln <= 16 &&
+                                      ((prev < 0.0 && sd >= 0.0) || (prev > 0.0 && sd <= 0.0)));
+#pragma unroll 1
+    while (cm && nc < 2) {
+        const int k = __builtin_ctzll(cm);
+        cm &= cm - 1;
+        double lo = (k - 1) / 16.0, hi = k / 16.0, flo = wv.bcast(sd, k - 1);
+#pragma unroll 1
+        for (int it = 0; it < kMultisect; ++it) {
+            double mu, mv, mdu, mdv;
+            curve_eval(cv, lo + (hi - lo) * (ln + 1) / 65.0, mu, mv, mdu, mdv);
+            const double fm = (mu - fr.cu) * fr.ew_v - (mv - fr.cv) * fr.ew_u;
+            // the first point past the sign change (64: none, the root lies
+            // beyond the last point)
+            const unsigned long long dm = wv.ballot((flo < 0.0) != (fm < 0.0));
+            const int i = dm ? __builtin_ctzll(dm) : 64;
+            const double fb = wv.bcast(fm, i > 0 ? i - 1 : 0);
+            const double nlo = i > 0 ? lo + (hi - lo) * i / 65.0 : lo;
+            const double nhi = i < 64 ? lo + (hi - lo) * (i + 1) / 65.0 : hi;
+            if (i > 0) flo = fb;
+            lo = nlo;
+            hi = nhi;
         }
-        prev = sd;
+        const double tr = 0.5 * (lo + hi);
+        double ru, rv, rdu, rdv;
+        curve_eval(cv, tr, ru, rv, rdu, rdv);
+        const double rr = sqrt((ru - fr.cu) * (ru - fr.cu) + (rv - fr.cv) * (rv - fr.cv));
+        const double speed = sqrt(rdu * rdu + rdv * rdv);
+        centres[nc] = tr;
+        widths[nc++] = speed > 0.0 ? fmax(fr.anis * rr, fr.dparam) / speed : 1.0;
     }
     {
         auto near2 = [&](double t) {
@@ -447,12 +596,16 @@ GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__res
             return (u - fr.cu) * (u - fr.cu) + (v - fr.cv) * (v - fr.cv);
         };
         double a = fmax(best - 1, 0) / 16.0, b = fmin(best + 1, 16) / 16.0;
-        const double gr = 0.6180339887498949;
-        double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
-        double f1 = near2(x1), f2 = near2(x2);
-        for (int it = 0; it < 40; ++it) {
-            if (f1 < f2) { b = x2; x2 = x1; f2 = f1; x1 = b - gr * (b - a); f1 = near2(x1); }
-            else { a = x1; x1 = x2; f1 = f2; x2 = a + gr * (b - a); f2 = near2(x2); }
+#pragma unroll 1
+        for (int it = 0; it < kMultimin; ++it) {
+            double fm = near2(a + (b - a) * ln / 63.0);
+            if (!(fm < INFINITY)) fm = INFINITY;
+            int im = ln;
+            argmin64(wv, fm, im);
+            const int i0 = im > 0 ? im - 1 : 0, i1 = im < 63 ? im + 1 : 63;
+            const double na = a + (b - a) * i0 / 63.0, nb = a + (b - a) * i1 / 63.0;
+            a = na;
+            b = nb;
         }
         double tc = 0.5 * (a + b);
         const double fc = near2(tc), f0 = near2(0.0), fe = near2(1.0);
@@ -470,54 +623,40 @@ GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__res
             double t = centres[j]; centres[j] = centres[j - 1]; centres[j - 1] = t;
             t = widths[j]; widths[j] = widths[j - 1]; widths[j - 1] = t;
         }
-    {   // merge centres that lie within each other's first panel (keep the finer)
-        int m = 0;
-        for (int k = 0; k < nc; ++k) {
-            if (m > 0 && centres[k] - centres[m - 1] <= fmax(widths[k], widths[m - 1])) {
-                if (widths[k] < widths[m - 1]) { centres[m - 1] = centres[k]; widths[m - 1] = widths[k]; }
-                continue;
-            }
-            centres[m] = centres[k];
-            widths[m] = widths[k];
-            ++m;
+    int m = 0;   // merge centres within each other's first panel (keep the finer)
+    for (int k = 0; k < nc; ++k) {
+        if (m > 0 && centres[k] - centres[m - 1] <= fmax(widths[k], widths[m - 1])) {
+            if (widths[k] < widths[m - 1]) { centres[m - 1] = centres[k]; widths[m - 1] = widths[k]; }
+            continue;
         }
-        nc = m;
+        centres[m] = centres[k];
+        widths[m] = widths[k];
+        ++m;
     }
-    // integrand at t with its error: |cross| times the radial estimate, the
-    // radial integral taken to tol_f / |cross|
-    const double qnorm = sqrt(qx * qx + qy * qy + qz * qz);
-    auto integrand = [&](double t, double tol_f, double &err_f, double &rnd_f) {
-        double pu, pv, pdu, pdv;
-        curve_eval(cv, t, pu, pv, pdu, pdv);
-        const double ru = pu - fr.cu, rv = pv - fr.cv;
-        const double cr = ru * pdv - rv * pdu;
-        err_f = 0.0;
-        rnd_f = 0.0;
-        if (cr == 0.0) return 0.0;
-        double eH = 0.0, rH = 0.0;
-        const double H = radial(Q, h, fr.cu, fr.cv, ru, rv, qx, qy, qz, fr.dist, fr.Su, fr.Sv, tol_f / fabs(cr), qnorm,
-                                B, eH, rH, ovf, ctr, count);
-        err_f = fabs(cr) * eH;
-        rnd_f = fabs(cr) * rH;
-        return cr * H;
-    };
+    return m;
+}
+
+// Outer integral over one boundary curve (count_only: the number of its
+// initial panels, for the budget).
+template <class Wv, class CtrT>
+GWN_HD inline double curve_contribution(const Wv &wv, const QuadTables &Q, const double *__restrict__ h,
+                                        const Curve2 &cv, const NearFrame &fr, double qx, double qy, double qz,
+                                        bool count_only, Budget &B, bool &ovf, CtrT &ctr, bool count)
+{
+    double centres[3], widths[3];
+    const int nc = curve_centres(wv, cv, fr, centres, widths);
     // first panel at most 1/4 of the curve; 1/8 at a collapsed edge (pole),
     // where the integrand is near-singular along the whole edge
     const double first = fr.anis < 0.2 ? 0.125 : 0.25;
-    if (count_only) {   // the number of initial panels, for the budget
-        int npanels = 0;
-        for (int k = 0; k < nc; ++k) {
-            const double lo = k == 0 ? 0.0 : 0.5 * (centres[k - 1] + centres[k]);
-            const double hi = k == nc - 1 ? 1.0 : 0.5 * (centres[k] + centres[k + 1]);
-            npanels += count_panels(lo, hi, centres[k], fmin(widths[k], first));
-        }
-        return (double)npanels;
-    }
     double total = 0.0;
+    const double qnorm = sqrt(qx * qx + qy * qy + qz * qz);
+#pragma unroll 1
     for (int k = 0; k < nc; ++k) {
         const double lo = k == 0 ? 0.0 : 0.5 * (centres[k - 1] + centres[k]);
         const double hi = k == nc - 1 ? 1.0 : 0.5 * (centres[k] + centres[k + 1]);
-        total += graded_panels(Q, lo, hi, centres[k], fmin(widths[k], first), B, ovf, integrand);
+        if (count_only) total += count_panels(lo, hi, centres[k], fmin(widths[k], first));
+        else total += graded_panels(wv, Q, h, cv, fr, qx, qy, qz, qnorm, lo, hi, centres[k], fmin(widths[k], first),
+                                    B, ovf, ctr, count);
     }
     return total;
 }
@@ -526,19 +665,57 @@ GWN_HD inline double curve_contribution(const QuadTables &Q, const double *__res
 constexpr int kFootGrid = 9;
 constexpr double kFootStep = 1.0 / (kFootGrid - 1);
 
-// Foot point of q on the untrimmed patch: kFootGrid^2 samples, then projected
-// Gauss-Newton steps with step halving from the best sample and from the
-// best one away from it (the distance can have several local minima on
-// strongly non-uniform or folded patches).
-// Returns the squared distance and (u, v) the parameters; (ou, ov, od) the
-// other converged minimum (possibly the same point).
-GWN_HD inline double gauss_newton_foot(const double *__restrict__ h, double qx, double qy, double qz, double &bu,
-                                       double &bv, double bd)
+// Foot point of q on the untrimmed patch: the best of kFootGrid^2 samples
+// and the best one outside its 5 x 5 neighbourhood (the distance can have
+// several local minima on strongly non-uniform or folded patches), each
+// refined by projected Gauss-Newton steps, the step halved up to 7 times
+// until the distance falls.  Lanes 0-31 refine the first start, lanes 32-63
+// the second; the line search tries its 8 step lengths on 8 lanes at once
+// and takes the longest that lowers the distance.
+// Returns the squared distance and (bu, bv) the parameters; (ou, ov, od)
+// the other converged minimum (possibly the same point).
+template <class Wv>
+GWN_HD inline double foot_point3d(const Wv &wv, const double *__restrict__ h, double qx, double qy, double qz,
+                                  double &bu, double &bv, double &ou, double &ov, double &od)
 {
-    double r[3], Su[3], Sv[3];
+    const int ln = wv.lane();
+    constexpr int NS = kFootGrid * kFootGrid;
+    double dk[2] = {INFINITY, INFINITY};
+#pragma unroll 1
+    for (int r = 0; r < 2; ++r) {
+        const int k = ln + 64 * r;
+        if (k < NS) {
+            const int i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
+            HomEval e;
+            hom_eval(h, kFootStep * i, kFootStep * j, qx, qy, qz, e);
+            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
+            dk[r] = d2 < INFINITY ? d2 : INFINITY;
+        }
+    }
+    double d1 = dk[0];
+    int k1 = ln;
+    if (dk[1] < d1) { d1 = dk[1]; k1 = ln + 64; }
+    argmin64(wv, d1, k1);
+    const int i1 = k1 / kFootGrid, j1 = k1 - kFootGrid * (k1 / kFootGrid);
+    auto outside = [&](int k) {
+        const int i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
+        return abs(i - i1) > 2 || abs(j - j1) > 2;
+    };
+    double d2b = outside(ln) ? dk[0] : INFINITY;
+    int k2 = ln;
+    if (outside(ln + 64) && dk[1] < d2b) { d2b = dk[1]; k2 = ln + 64; }
+    argmin64(wv, d2b, k2);
+    const int i2 = k2 / kFootGrid, j2 = k2 - kFootGrid * (k2 / kFootGrid);
+    const int half = ln >> 5, hl = ln & 31;
+    double u = half ? kFootStep * i2 : kFootStep * i1, v = half ? kFootStep * j2 : kFootStep * j1;
+    double d = half ? d2b : d1;
+    bool active = d < INFINITY;
+#pragma unroll 1
     for (int it = 0; it < 16; ++it) {
+        if (!wv.ballot(active)) break;
         HomEval e;
-        hom_eval(h, bu, bv, qx, qy, qz, e);
+        double r[3], Su[3], Sv[3];
+        hom_eval(h, u, v, qx, qy, qz, e);
         euclid(e, r, Su, Sv);
         const double a = Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2];
         const double b = Su[0] * Sv[0] + Su[1] * Sv[1] + Su[2] * Sv[2];
@@ -549,54 +726,40 @@ GWN_HD inline double gauss_newton_foot(const double *__restrict__ h, double qx, 
         double du, dv;
         if (fabs(det) > 1e-300) { du = -(c * gu - b * gv) / det; dv = -(a * gv - b * gu) / det; }
         else { du = -gu / (a + 1e-300); dv = -gv / (c + 1e-300); }
-        double step = 1.0;
-        bool moved = false;
-        for (int ls = 0; ls < 8; ++ls) {
-            const double nu = fmin(1.0, fmax(0.0, bu + step * du)), nv = fmin(1.0, fmax(0.0, bv + step * dv));
+        double nu = u, nv = v, nd = d;
+        bool ok = false;
+        if (active && hl < 8) {
+            const double step = 1.0 / (1 << hl);
+            nu = fmin(1.0, fmax(0.0, u + step * du));
+            nv = fmin(1.0, fmax(0.0, v + step * dv));
             HomEval f;
             hom_eval(h, nu, nv, qx, qy, qz, f);
-            const double d2 = (f.A[0] * f.A[0] + f.A[1] * f.A[1] + f.A[2] * f.A[2]) / (f.W * f.W);
-            if (d2 < bd) { bd = d2; bu = nu; bv = nv; moved = true; break; }
-            step *= 0.5;
+            nd = (f.A[0] * f.A[0] + f.A[1] * f.A[1] + f.A[2] * f.A[2]) / (f.W * f.W);
+            ok = nd < d;
         }
-        if (!moved || step * (fabs(du) + fabs(dv)) < 1e-15) break;
+        const unsigned hm = (unsigned)(wv.ballot(ok) >> (32 * half)) & 0xffu;
+        const int s = hm ? __builtin_ctz(hm) : 0;
+        const double su = wv.shfl(nu, 32 * half + s), sv = wv.shfl(nv, 32 * half + s), sdd = wv.shfl(nd, 32 * half + s);
+        if (active) {
+            if (hm) {
+                u = su;
+                v = sv;
+                d = sdd;
+                if ((1.0 / (1 << s)) * (fabs(du) + fabs(dv)) < 1e-15) active = false;
+            } else {
+                active = false;
+            }
+        }
     }
-    return bd;
-}
-
-GWN_HD inline double foot_point3d(const double *__restrict__ h, double qx, double qy, double qz, double &bu,
-                                  double &bv, double &ou, double &ov, double &od)
-{
-    // best sample, then the best one outside its 5 x 5 neighbourhood (a
-    // start in another basin when the distance has a second minimum); one
-    // loop over both passes, so the patch evaluation is inlined once
-    double d1 = INFINITY, d2b = INFINITY, u1 = 0.5, v1 = 0.5, u2 = 0.5, v2 = 0.5;
-    int i1 = 0, j1 = 0;
-#pragma unroll 1
-    for (int t = 0; t < 2 * kFootGrid * kFootGrid; ++t) {
-        const bool second = t >= kFootGrid * kFootGrid;
-        const int k = second ? t - kFootGrid * kFootGrid : t, i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
-        if (second && abs(i - i1) <= 2 && abs(j - j1) <= 2) continue;
-        HomEval e;
-        hom_eval(h, kFootStep * i, kFootStep * j, qx, qy, qz, e);
-        const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
-        if (!second && d2 < d1) { d1 = d2; u1 = kFootStep * i; v1 = kFootStep * j; i1 = i; j1 = j; }
-        if (second && d2 < d2b) { d2b = d2; u2 = kFootStep * i; v2 = kFootStep * j; }
-    }
-#pragma unroll 1
-    for (int k = 0; k < 2; ++k) {
-        double u = k ? u2 : u1, v = k ? v2 : v1, d = k ? d2b : d1;
-        if (d < INFINITY) d = gauss_newton_foot(h, qx, qy, qz, u, v, d);
-        if (k) { u2 = u; v2 = v; d2b = d; } else { u1 = u; v1 = v; d1 = d; }
-    }
-    double bd = d1;
+    const double u1 = wv.bcast(u, 0), v1 = wv.bcast(v, 0), e1 = wv.bcast(d, 0);
+    const double u2 = wv.bcast(u, 32), v2 = wv.bcast(v, 32), e2 = wv.bcast(d, 32);
     bu = u1;
     bv = v1;
     ou = u2;
     ov = v2;
-    od = d2b;
-    if (d2b < d1) { bd = d2b; bu = u2; bv = v2; ou = u1; ov = v1; od = d1; }
-    return bd;
+    od = e2;
+    if (e2 < e1) { bu = u2; bv = v2; ou = u1; ov = v1; od = e1; return e2; }
+    return e1;
 }
 
 // Polar frame at the foot point (cu, cv) with squared distance d2.
@@ -615,17 +778,29 @@ GWN_HD inline NearFrame near_frame(const double *__restrict__ h, double cu, doub
     const bool on_surface = sqrt(d2) < eps_on;
     fr.dist = on_surface ? 1e300 : sqrt(d2);
     // metric J^T J at c: eigenvalues l1 <= l2; weak direction perpendicular
-    // to the major axis at angle atan2(2 gb, ga - gc) / 2 (stable also when
-    // gb is pure roundoff)
+    // to the major axis, at angle theta = atan2(2 gb, ga - gc) / 2, whose
+    // sine and cosine come from the half-angle identities (the branch on the
+    // sign of ga - gc keeps them accurate; stable also when gb is pure
+    // roundoff)
     const double *Su = fr.Su, *Sv = fr.Sv;
     const double ga = Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2];
     const double gb = Su[0] * Sv[0] + Su[1] * Sv[1] + Su[2] * Sv[2];
     const double gc = Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2];
     const double tr = 0.5 * (ga + gc), df = sqrt(fmax(0.25 * (ga - gc) * (ga - gc) + gb * gb, 0.0));
     const double l2 = tr + df, l1 = fmax(tr - df, 0.0);
-    const double theta = 0.5 * atan2(2.0 * gb, ga - gc);
-    fr.ew_u = -sin(theta);
-    fr.ew_v = cos(theta);
+    const double x2 = ga - gc, y2 = 2.0 * gb, r2 = 2.0 * df;   // r2 = |(x2, y2)|
+    double ct = 1.0, st = 0.0;
+    if (r2 > 0.0) {
+        if (x2 >= 0.0) {
+            ct = sqrt(0.5 * (1.0 + x2 / r2));
+            st = y2 / (2.0 * r2 * ct);
+        } else {
+            st = copysign(sqrt(0.5 * (1.0 - x2 / r2)), y2);
+            ct = y2 / (2.0 * r2 * st);
+        }
+    }
+    fr.ew_u = -st;
+    fr.ew_v = ct;
     fr.anis = l2 > 0.0 ? sqrt(l1 / l2) : 1.0;
     fr.dparam = l2 > 0.0 ? fmax(sqrt(d2), eps_on) / sqrt(l2) : 1.0;
     return fr;
@@ -709,42 +884,48 @@ constexpr int kMaxCross = 32;   // crossings of a trimmed leaf's loops with a cu
 // mean of the values at q +- delta n (n the unit normal at the foot point,
 // delta = 1e3 eps_on), each under the same error control; where the foot
 // point is trimmed away the value is continuous and the mean is the value.
-template <bool COUNT, class CtrT>
-GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, const Prim3 *__restrict__ P,
-                                                           const Trim3 *__restrict__ trims, double qx, double qy,
-                                                           double qz, double eps_on, double tol, bool &ovf,
-                                                           CtrT &ctr)
+// Called by all 64 lanes of a wave with the same arguments; every lane
+// returns the same value and ovf.
+template <bool COUNT, class Wv, class CtrT>
+GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__restrict__ P,
+                            const Trim3 *__restrict__ trims, double qx, double qy, double qz, double eps_on,
+                            double tol, bool &ovf, CtrT &ctr)
 {
     const double *__restrict__ h = P->h;
-    double bu, bv, ou, ov, od;
-    double bd = foot_point3d(h, qx, qy, qz, bu, bv, ou, ov, od);
+    const int nt = P->trim_count;
+    const Trim3 *__restrict__ tr = trims + P->trim_begin;
+    double bu = 0.5, bv = 0.5, ou = 0.5, ov = 0.5, od = INFINITY, bd = INFINITY;
     double mean = 0.0;
     int sides = 1;
     double nrm[3] = {0.0, 0.0, 0.0};
-    if (sqrt(bd) < eps_on) {
-        HomEval e;
-        double r[3], Su[3], Sv[3];
-        hom_eval(h, bu, bv, qx, qy, qz, e);
-        euclid(e, r, Su, Sv);
-        nrm[0] = Su[1] * Sv[2] - Su[2] * Sv[1];
-        nrm[1] = Su[2] * Sv[0] - Su[0] * Sv[2];
-        nrm[2] = Su[0] * Sv[1] - Su[1] * Sv[0];
-        const double nn = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
-        if (nn > 0.0) {
-            sides = 2;
-            for (int a = 0; a < 3; ++a) nrm[a] *= 1e3 * eps_on / nn;
-        }
-    }
     const double q0[3] = {qx, qy, qz};
+    // step 0 finds the foot point of q; steps 1 .. sides integrate about q
+    // itself, or about q + delta n and q - delta n when q is on the surface
 #pragma unroll 1
-    for (int side = 0; side < sides; ++side) {
-        if (sides == 2) {
-            qx = q0[0] + (side ? -nrm[0] : nrm[0]);
-            qy = q0[1] + (side ? -nrm[1] : nrm[1]);
-            qz = q0[2] + (side ? -nrm[2] : nrm[2]);
-            bd = foot_point3d(h, qx, qy, qz, bu, bv, ou, ov, od);
+    for (int step = 0; step <= sides; ++step) {
+        if (step > 0 && sides == 2) {
+            qx = q0[0] + (step == 1 ? nrm[0] : -nrm[0]);
+            qy = q0[1] + (step == 1 ? nrm[1] : -nrm[1]);
+            qz = q0[2] + (step == 1 ? nrm[2] : -nrm[2]);
         }
-        const int nt = P->trim_count;
+        if (step == 0 || sides == 2) bd = foot_point3d(wv, h, qx, qy, qz, bu, bv, ou, ov, od);
+        if (step == 0) {
+            if (sqrt(bd) < eps_on) {
+                HomEval e;
+                double r[3], Su[3], Sv[3];
+                hom_eval(h, bu, bv, qx, qy, qz, e);
+                euclid(e, r, Su, Sv);
+                nrm[0] = Su[1] * Sv[2] - Su[2] * Sv[1];
+                nrm[1] = Su[2] * Sv[0] - Su[0] * Sv[2];
+                nrm[2] = Su[0] * Sv[1] - Su[1] * Sv[0];
+                const double nn = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+                if (nn > 0.0) {
+                    sides = 2;
+                    for (int a = 0; a < 3; ++a) nrm[a] *= 1e3 * eps_on / nn;
+                }
+            }
+            continue;
+        }
         bool split = false;
         if (fabs(ou - bu) + fabs(ov - bv) > 0.05 && od < INFINITY) {
             double p[3] = {0.0, 0.0, 0.0}, sep2 = 0.0;
@@ -775,8 +956,7 @@ GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, 
 #pragma unroll 1
             for (int k = 0; k < nt && split; ++k) {
                 Curve2 cv;
-                const Trim3 *t = trims + P->trim_begin + k;
-                for (int m = 0; m < 9; ++m) cv.h[m] = t->h[m];
+                for (int m = 0; m < 9; ++m) cv.h[m] = tr[k].h[m];
                 double r[2];
                 int nr = 0;
                 if (!cut_roots(cv, dir, cut, r, nr) || ncr + nr > kMaxCross) { split = false; break; }
@@ -804,73 +984,58 @@ GWN_HD __attribute__((always_inline)) inline double near3d(const QuadTables &Q, 
             }
         }
         // The leaf's budget tol is spent panel by panel over all its boundary
-        // curves: first the panels are counted, then integrated.
+        // curves: first the panels are counted (pass 0), then integrated.
+        // The boundary of a part: the square's (or its half's) four edges;
+        // else the trim curves, each cut into up to three pieces when the
+        // leaf is split, and the stretches of the cut line.
         const int nparts = split ? 2 : 1;
-        NearFrame frs[2];
-        double rect[2][4];
-        bool lowside[2] = {true, true};
-#pragma unroll 1
-        for (int part = 0; part < nparts; ++part) {
-            const double cu = part ? ou : bu, cv = part ? ov : bv, d2 = part ? od : bd;
-            double u0 = 0.0, u1 = 1.0, v0 = 0.0, v1 = 1.0;
-            if (split) {
-                const bool low = (cut_u ? cu : cv) < cut;
-                lowside[part] = low;
-                if (cut_u) { if (low) u1 = cut; else u0 = cut; }
-                else { if (low) v1 = cut; else v0 = cut; }
-            }
-            rect[part][0] = u0; rect[part][1] = u1; rect[part][2] = v0; rect[part][3] = v1;
-            frs[part] = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
-        }
+        const int ncurves = nt == 0 ? 4 : split ? 3 * nt + ncr / 2 : nt;
         Budget B{tol, 0, 0};
         double total = 0.0;
 #pragma unroll 1
         for (int pass = 0; pass < 2; ++pass) {
-            const bool count_only = pass == 0;
-            auto integrate = [&](int part, const Curve2 &crv) {
-                const double r = curve_contribution(Q, h, crv, frs[part], qx, qy, qz, count_only, B, ovf, ctr, COUNT);
-                if (count_only) B.left += (int)r; else total += r;
-            };
 #pragma unroll 1
             for (int part = 0; part < nparts; ++part) {
-                if (nt == 0) {
-#pragma unroll 1
-                    for (int k = 0; k < 4; ++k)
-                        integrate(part, rect_edge(rect[part][0], rect[part][1], rect[part][2], rect[part][3], k));
-                    continue;
+                const double cu = part ? ou : bu, cv = part ? ov : bv, d2 = part ? od : bd;
+                double u0 = 0.0, u1 = 1.0, v0 = 0.0, v1 = 1.0;
+                const bool low = (cut_u ? cu : cv) < cut;
+                if (split) {
+                    if (cut_u) { if (low) u1 = cut; else u0 = cut; }
+                    else { if (low) v1 = cut; else v0 = cut; }
                 }
+                const NearFrame fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
+                // stretches of the cut line inside the region, walked with this
+                // half on the left: +y for the low half of a u cut and the high
+                // half of a v cut
+                const bool up = (dir == 0) == low;
 #pragma unroll 1
-                for (int k = 0; k < nt; ++k) {
+                for (int it = 0; it < ncurves; ++it) {
                     Curve2 crv;
-                    const Trim3 *t = trims + P->trim_begin + k;
-                    for (int m = 0; m < 9; ++m) crv.h[m] = t->h[m];
-                    if (!split) {
-                        integrate(part, crv);
-                        continue;
-                    }
-                    double r[2];
-                    int nr = 0;
-                    cut_roots(crv, dir, cut, r, nr);
-#pragma unroll 1
-                    for (int j = 0; j <= nr; ++j) {
+                    if (nt == 0) {
+                        crv = rect_edge(u0, u1, v0, v1, it);
+                    } else if (!split) {
+                        for (int m = 0; m < 9; ++m) crv.h[m] = tr[it].h[m];
+                    } else if (it < 3 * nt) {
+                        const int k = it / 3, j = it - 3 * (it / 3);
+                        Curve2 whole;
+                        for (int m = 0; m < 9; ++m) whole.h[m] = tr[k].h[m];
+                        double r[2];
+                        int nr = 0;
+                        cut_roots(whole, dir, cut, r, nr);
+                        if (j > nr) continue;
                         const double t0 = j == 0 ? 0.0 : r[j - 1], t1 = j == nr ? 1.0 : r[j];
                         double u, v, du, dv;
-                        curve_eval(crv, 0.5 * (t0 + t1), u, v, du, dv);
-                        if (((dir == 0 ? u : v) < cut) != lowside[part]) continue;
-                        integrate(part, nr ? sub_curve(crv, t0, t1) : crv);
-                    }
-                }
-                if (split) {
-                    // stretches of the cut line inside the region, walked with this
-                    // half on the left: +y for the low half of a u cut and the high
-                    // half of a v cut
-                    const bool up = (dir == 0) == lowside[part];
-#pragma unroll 1
-                    for (int i = 0; i + 1 < ncr; i += 2) {
+                        curve_eval(whole, 0.5 * (t0 + t1), u, v, du, dv);
+                        if (((dir == 0 ? u : v) < cut) != low) continue;
+                        crv = nr ? sub_curve(whole, t0, t1) : whole;
+                    } else {
+                        const int i = 2 * (it - 3 * nt);
                         const double ya = ycr[i], yb = -ycr[i + 1] - 2.0;
                         const double y0 = up ? ya : yb, y1 = up ? yb : ya;
-                        integrate(part, dir == 0 ? rect_edge(cut, cut, y0, y1, 1) : rect_edge(y0, y1, cut, cut, 0));
+                        crv = dir == 0 ? rect_edge(cut, cut, y0, y1, 1) : rect_edge(y0, y1, cut, cut, 0);
                     }
+                    const double r = curve_contribution(wv, Q, h, crv, fr, qx, qy, qz, pass == 0, B, ovf, ctr, COUNT);
+                    if (pass == 0) B.left += (int)r; else total += r;
                 }
             }
         }

@@ -317,17 +317,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     flush_counters<COUNT>(ctr, counters);
 }
 
-// Pass 2 (3D): the near-field leaves of one wave's queries, one (query,
-// leaf) pair per lane, then classification and scatter.  The pairs of the
-// wave are numbered query by query in the traversal's order; lane j of a
-// round of 64 takes pair base + j.  Each query then adds its pairs' values
-// one by one in that order, so its result does not depend on its wave or
-// batch mates.  Mixed form, first pass: lanes with |w - 0.5| < band are
-// flagged for the FP64 re-evaluation instead of written.
-// One wave per workgroup: at one wave per SIMD (register bound) a workgroup
-// of four waves holds a whole CU until its slowest wave ends, and the waves'
-// pair counts differ widely; single-wave workgroups let each SIMD take the
-// next wave as soon as its own is done.
+// Pass 2 (3D): the near-field leaves of one wave's queries.  The wave takes
+// their (query, leaf) pairs one at a time, query by query in the
+// traversal's order, and all 64 lanes evaluate each pair together (the
+// rule's integrand evaluations are shared out over the lanes, its control
+// is the same on all of them).  Each query adds its pairs' values one by
+// one in that order, so its result does not depend on its wave or batch
+// mates.  Then classification and scatter.  Mixed form, first pass: lanes
+// with |w - 0.5| < band are flagged for the FP64 re-evaluation instead of
+// written.
+// One wave per workgroup: the waves' pair counts differ widely, and
+// single-wave workgroups let each SIMD take the next wave as soon as its
+// own is done.
 template <bool COUNT, bool RECLASS>
 __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
                                                const double *__restrict__ pts, double *__restrict__ out_w,
@@ -351,46 +352,28 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
     const double qz = act ? pts[3 * (int64_t)row + 2] : 0.0;
     const int full = act ? NS.cnt[slot] : 0;
     const int c = min(full, kNearSlots);
-    // inclusive prefix sum of the pair counts over the wave
-    int incl = c;
-    for (int d = 1; d < 64; d <<= 1) {
-        const int v = __shfl_up(incl, d);
-        if (lane >= d) incl += v;
-    }
-    const int excl = incl - c;
-    const int total = __shfl(incl, 63);
     Ctr ctr;
 #pragma unroll
     for (int k = 0; k < GWN_NCOUNTERS; ++k) ctr.v[k] = 0;
+    const DevWave wv;
+    const Prim3 *__restrict__ prims = (const Prim3 *)M.prims;
+    const Trim3 *__restrict__ trims = (const Trim3 *)M.trims;
+    const Node3 *__restrict__ nodes = (const Node3 *)M.nodes;
+    const double tol = 4.0 * kPi * M.eps_q;
     double near_sum = 0.0;
-    for (int base = 0; base < total; base += 64) {
-        const int t = base + lane;
-        const bool has = t < total;
-        // owner: the first lane with incl > t, i.e. the number of lanes with
-        // incl <= t (incl is non-decreasing); the same six shuffles on every
-        // lane, so no lane reads from one that has left the search
-        int owner = 0;
-        for (int step = 32; step > 0; step >>= 1)
-            if (__shfl(incl, owner + step - 1) <= t) owner += step;
-        const int oexcl = __shfl(excl, owner);
-        const double ox = __shfl(qx, owner), oy = __shfl(qy, owner), oz = __shfl(qz, owner);
-        double v = 0.0;
-        if (has) {
-            const int node = NS.list[((int64_t)wave * T.qpw + owner) * kNearSlots + (t - oexcl)];
-            const Node3 *nd = (const Node3 *)M.nodes + node;
-            const int leaf = -1 - nd->right;
+    unsigned long long todo = __ballot(act && c > 0);
+    while (todo) {
+        const int j = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int cj = wv.bcast(c, j);
+        const double ox = wv.bcast(qx, j), oy = wv.bcast(qy, j), oz = wv.bcast(qz, j);
+        const int32_t *__restrict__ list = NS.list + ((int64_t)wave * T.qpw + j) * kNearSlots;
+        for (int k = 0; k < cj; ++k) {
+            const int leaf = uniform_i(-1 - nodes[list[k]].right);
             bool budget = false;   // a panel or piece missed its share of 4 pi eps_q
-            v = near3d<COUNT>(c_quad, (const Prim3 *)M.prims + leaf, (const Trim3 *)M.trims, ox, oy, oz, M.eps_on,
-                              4.0 * kPi * M.eps_q, budget, ctr);
+            double v = near3d<COUNT>(wv, c_quad, prims + leaf, trims, ox, oy, oz, M.eps_on, tol, budget, ctr);
             if (budget) v = NAN;
-        }
-        // this round holds pairs [max(excl, base), min(incl, base + 64)) of each lane
-        const int a = max(excl, base) - base, b = min(incl, base + 64) - base;
-        int span = b > a ? b - a : 0;
-        for (int off = 32; off > 0; off >>= 1) span = max(span, __shfl_xor(span, off));
-        for (int k = 0; k < span; ++k) {
-            const double x = __shfl(v, min(a + k, 63));
-            if (a + k < b) near_sum += x;
+            if (lane == j) near_sum += v;
         }
     }
     if (act) {
