@@ -123,22 +123,36 @@ GWN_HD inline void hom_eval(const double *__restrict__ h, double u, double v, do
     cubic_b(u, bu, du);
     cubic_b(v, bv, dv);
     double H[4] = {0, 0, 0, 0}, Hu[4] = {0, 0, 0, 0}, Hv[4] = {0, 0, 0, 0};
-#pragma unroll
+    // one row of the control net (16 values) at a time: the net is the same
+    // on all lanes and is read with scalar loads row by row, so it never has
+    // to be held whole.  On the device it is read through the constant
+    // address space (it does not change during a launch), where a load from
+    // a wave-uniform address always becomes a scalar load.
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) double *NetPtr;
+    const NetPtr net = (NetPtr)(unsigned long long)h;
+#else
+    const double *__restrict__ net = h;
+#endif
+#pragma unroll 1
     for (int i = 0; i < 4; ++i) {
+        const double bi = i == 0 ? bu[0] : i == 1 ? bu[1] : i == 2 ? bu[2] : bu[3];
+        const double di = i == 0 ? du[0] : i == 1 ? du[1] : i == 2 ? du[2] : du[3];
+        const auto row = net + 16 * i;
         double r[4] = {0, 0, 0, 0}, rv[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const double c = h[16 * i + 4 * j + k];
+                const double c = row[4 * j + k];
                 r[k] = fma(bv[j], c, r[k]);
                 rv[k] = fma(dv[j], c, rv[k]);
             }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            H[k] = fma(bu[i], r[k], H[k]);
-            Hu[k] = fma(du[i], r[k], Hu[k]);
-            Hv[k] = fma(bu[i], rv[k], Hv[k]);
+            H[k] = fma(bi, r[k], H[k]);
+            Hu[k] = fma(di, r[k], Hu[k]);
+            Hv[k] = fma(bi, rv[k], Hv[k]);
         }
     }
     e.W = H[3]; e.Wu = Hu[3]; e.Wv = Hv[3];
@@ -231,32 +245,74 @@ struct DevWave {
     }
     __device__ int bcast(int x, int src) const { return __builtin_amdgcn_readlane(x, src); }
     __device__ unsigned long long ballot(bool p) const { return __ballot(p); }
-};
-
-// Sum over the caller's group of 16 lanes (a butterfly: every lane of the
-// group gets the same bits).
-template <class Wv>
-GWN_HD inline double sum16(const Wv &wv, double x)
-{
-    x += wv.shfl_xor(x, 8);
-    x += wv.shfl_xor(x, 4);
-    x += wv.shfl_xor(x, 2);
-    x += wv.shfl_xor(x, 1);
-    return x;
-}
-
-// Minimum of d over the wave and its index k (the smaller k on ties).
-template <class Wv>
-GWN_HD inline void argmin64(const Wv &wv, double &d, int &k)
-{
-    for (int m = 32; m > 0; m >>= 1) {
-        const double od = wv.shfl_xor(d, m);
-        const int ok = wv.shfl_xor(k, m);
+    // sum over the lane's group of 16 by DPP row moves: pairs, quads (quad
+    // permutes), then the two quads of each half row (half mirror), then the
+    // two half rows (mirror); every lane of the row gets the same bits
+    __device__ double sum16(double x) const
+    {
+        x += dpp<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+        x += dpp<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+        x += dpp<0x141>(x);   // row_half_mirror
+        x += dpp<0x140>(x);   // row_mirror
+        return x;
+    }
+    // minimum of d over the wave with its index k (the smaller k on ties; an
+    // exact total order, so the order of the steps does not matter): DPP
+    // steps within each row of 16, then the four rows' results
+    __device__ void argmin(double &d, int &k) const
+    {
+        argmin_step<0xB1>(d, k);
+        argmin_step<0x4E>(d, k);
+        argmin_step<0x141>(d, k);
+        argmin_step<0x140>(d, k);
+        double bd = bcast(d, 0);
+        int bk = bcast(k, 0);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            const double rd = bcast(d, 16 * r);
+            const int rk = bcast(k, 16 * r);
+            if (rd < bd || (rd == bd && rk < bk)) {
+                bd = rd;
+                bk = rk;
+            }
+        }
+        d = bd;
+        k = bk;
+    }
+    template <int CTRL>
+    __device__ static void argmin_step(double &d, int &k)
+    {
+        const double od = dpp<CTRL>(d);
+        const int ok = __builtin_amdgcn_update_dpp(0, k, CTRL, 0xf, 0xf, false);
         if (od < d || (od == d && ok < k)) {
             d = od;
             k = ok;
         }
     }
+    template <int CTRL>
+    __device__ static double dpp(double x)
+    {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+        return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+};
+
+// Sum over the caller's group of 16 lanes (every lane of the group gets the
+// same bits).
+template <class Wv>
+GWN_HD inline double sum16(const Wv &wv, double x)
+{
+    return wv.sum16(x);
+}
+
+// Minimum of d over the wave and its index k (the smaller k on ties; no NaN
+// in d).
+template <class Wv>
+GWN_HD inline void argmin64(const Wv &wv, double &d, int &k)
+{
+    wv.argmin(d, k);
 }
 
 GWN_HD inline int imin(int a, int b) { return a < b ? a : b; }
@@ -304,6 +360,34 @@ struct NearFrame {
     double anis;         // sqrt(l1 / l2)
 };
 
+constexpr int kMaxCross = 32;   // crossings of a trimmed leaf's loops with a cut
+
+// State of the rule kept in memory that the wave's lanes share (LDS on the
+// device), read where it is used rather than held in every lane's
+// registers through the integration: the polar frame of the part being
+// integrated and the crossings of a split leaf's trim loops with the cut.
+// Every lane writes the same values.
+constexpr int kCurveCache = 48;   // curves whose grading centres are kept between the two passes
+
+struct NearShared {
+    NearFrame fr;
+    double ycr[kMaxCross];
+    // per boundary curve of the leaf (both parts of a split leaf): number of
+    // grading centres, the centres and their first panel widths, found in
+    // the counting pass and reused in the integration pass
+    int ncen[kCurveCache];
+    double cen[kCurveCache][3], wid[kCurveCache][3];
+};
+
+// Compiler barrier: values stored to the shared state before it are read
+// back from memory after it, not carried in registers.
+GWN_HD inline void compiler_fence()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" ::: "memory");
+#endif
+}
+
 // Sub-panels of an outer panel whose nodes are integrated together: 9 nodes
 // each, three radial pieces per node, one task lane per piece.
 constexpr int kSubPerChunk = 2;
@@ -327,6 +411,7 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
                                 double sw, int sp0, int nc, double tol_f, Budget &B, bool &ovf, CtrT &ctr, bool count,
                                 double &f, double &ef, double &rf)
 {
+    compiler_fence();
     const int ln = wv.lane();
     const int M = kGKo * nc;
     const int m = ln / 3, p = ln - 3 * (ln / 3);
@@ -360,6 +445,10 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
     unsigned long long pend = wv.ballot(has && cr != 0.0 && p < np);
     long long evals = 0;
     const int g = ln >> 4, i = ln & 15;
+    // this lane's node of the radial rule: abscissa, Kronrod and Gauss weights
+    const double xr_i = Q.xr[i < kGKr ? i : 0];
+    const double wr_i = i < kGKr ? Q.wr[i] : 0.0;
+    const double gr_i = i < kGKr && (i & 1) ? Q.gr[i >> 1] : 0.0;
 #pragma unroll 1
     for (int l = 0; l <= kRadialLevels && pend; ++l) {
         const int nsub = 1 << l;
@@ -383,7 +472,7 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
             const bool node = vra && i < kGKr;
             double fx = 0.0, nz = 0.0;
             if (node) {
-                const double x = xa + w * Q.xr[i];
+                const double x = xa + w * xr_i;
                 double tau, jac;
                 if (tuni) {
                     tau = x;
@@ -400,8 +489,8 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
                 const double a2 = ev.A[0] * ev.A[0] + ev.A[1] * ev.A[1] + ev.A[2] * ev.A[2];
                 nz = fabs(fx) * (1.0 + (a2 > 0.0 ? qnorm * fabs(ev.W) / sqrt(a2) : 0.0));
             }
-            const double wk = node ? Q.wr[i] : 0.0;
-            const double wg = node && (i & 1) ? Q.gr[i >> 1] : 0.0;
+            const double wk = node ? wr_i : 0.0;
+            const double wg = node ? gr_i : 0.0;
             const double K = sum16(wv, wk * fx);
             const double G = sum16(wv, wg * fx);
             const double asc = sum16(wv, wk * fabs(fx - K));
@@ -541,6 +630,7 @@ template <class Wv>
 GWN_HD inline int curve_centres(const Wv &wv, const Curve2 &cv, const NearFrame &fr, double centres[3],
                                 double widths[3])
 {
+    compiler_fence();
     const int ln = wv.lane();
     int nc = 0;
     double d2 = INFINITY, sd;
@@ -637,14 +727,33 @@ GWN_HD inline int curve_centres(const Wv &wv, const Curve2 &cv, const NearFrame 
 }
 
 // Outer integral over one boundary curve (count_only: the number of its
-// initial panels, for the budget).
+// initial panels, for the budget).  Curve `slot` below kCurveCache keeps
+// its grading centres in the shared state from the counting pass to the
+// integration pass.
 template <class Wv, class CtrT>
 GWN_HD inline double curve_contribution(const Wv &wv, const QuadTables &Q, const double *__restrict__ h,
                                         const Curve2 &cv, const NearFrame &fr, double qx, double qy, double qz,
-                                        bool count_only, Budget &B, bool &ovf, CtrT &ctr, bool count)
+                                        bool count_only, Budget &B, bool &ovf, CtrT &ctr, bool count, NearShared &sh,
+                                        int slot)
 {
     double centres[3], widths[3];
-    const int nc = curve_centres(wv, cv, fr, centres, widths);
+    int nc;
+    if (!count_only && slot < kCurveCache) {
+        nc = sh.ncen[slot];
+        for (int k = 0; k < 3; ++k) {
+            centres[k] = sh.cen[slot][k];
+            widths[k] = sh.wid[slot][k];
+        }
+    } else {
+        nc = curve_centres(wv, cv, fr, centres, widths);
+        if (slot < kCurveCache) {
+            sh.ncen[slot] = nc;
+            for (int k = 0; k < 3; ++k) {
+                sh.cen[slot][k] = centres[k];
+                sh.wid[slot][k] = widths[k];
+            }
+        }
+    }
     // first panel at most 1/4 of the curve; 1/8 at a collapsed edge (pole),
     // where the integrand is near-singular along the whole edge
     const double first = fr.anis < 0.2 ? 0.125 : 0.25;
@@ -867,8 +976,6 @@ GWN_HD inline Curve2 sub_curve(const Curve2 &c, double t0, double t1)
     return r;
 }
 
-constexpr int kMaxCross = 32;   // crossings of a trimmed leaf's loops with a cut
-
 // Near-field solid angle of one (trimmed) patch at q.  When the distance to
 // the patch has a second local minimum (a fold, a wavy surface, or a
 // strongly non-uniform parametrisation that stretches the near-singular
@@ -889,10 +996,11 @@ constexpr int kMaxCross = 32;   // crossings of a trimmed leaf's loops with a cu
 template <bool COUNT, class Wv, class CtrT>
 GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__restrict__ P,
                             const Trim3 *__restrict__ trims, double qx, double qy, double qz, double eps_on,
-                            double tol, bool &ovf, CtrT &ctr)
+                            double tol, bool &ovf, CtrT &ctr, NearShared &sh)
 {
     const double *__restrict__ h = P->h;
     const int nt = P->trim_count;
+    double *__restrict__ ycr = sh.ycr;
     const Trim3 *__restrict__ tr = trims + P->trim_begin;
     double bu = 0.5, bv = 0.5, ou = 0.5, ov = 0.5, od = INFINITY, bd = INFINITY;
     double mean = 0.0;
@@ -950,7 +1058,6 @@ GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__re
         // crosses the line moving towards +x (dir 0) or -x (dir 1) starts such a
         // stretch, one moving the other way ends it.  A cut through a junction of
         // two curves or tangent to a loop is not taken (the leaf stays whole).
-        double ycr[kMaxCross];
         int ncr = 0;
         if (split && nt > 0) {
 #pragma unroll 1
@@ -1003,7 +1110,9 @@ GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__re
                     if (cut_u) { if (low) u1 = cut; else u0 = cut; }
                     else { if (low) v1 = cut; else v0 = cut; }
                 }
-                const NearFrame fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
+                sh.fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
+                compiler_fence();
+                const NearFrame &fr = sh.fr;
                 // stretches of the cut line inside the region, walked with this
                 // half on the left: +y for the low half of a u cut and the high
                 // half of a v cut
@@ -1034,7 +1143,8 @@ GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__re
                         const double y0 = up ? ya : yb, y1 = up ? yb : ya;
                         crv = dir == 0 ? rect_edge(cut, cut, y0, y1, 1) : rect_edge(y0, y1, cut, cut, 0);
                     }
-                    const double r = curve_contribution(wv, Q, h, crv, fr, qx, qy, qz, pass == 0, B, ovf, ctr, COUNT);
+                    const double r = curve_contribution(wv, Q, h, crv, fr, qx, qy, qz, pass == 0, B, ovf, ctr, COUNT,
+                                                        sh, part * ncurves + it);
                     if (pass == 0) B.left += (int)r; else total += r;
                 }
             }

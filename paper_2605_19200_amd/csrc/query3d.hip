@@ -328,9 +328,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 // written.
 // One wave per workgroup: the waves' pair counts differ widely, and
 // single-wave workgroups let each SIMD take the next wave as soon as its
-// own is done.
+// own is done.  Two waves per SIMD (256 registers each, some spilled) ran
+// the bodies grid 13 % faster than one wave with no spill; four (128
+// registers) were slower again.
 template <bool COUNT, bool RECLASS>
-__global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
                                                const double *__restrict__ pts, double *__restrict__ out_w,
                                                uint8_t *__restrict__ out_in, long long *counters)
 {
@@ -360,6 +362,7 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
     const Trim3 *__restrict__ trims = (const Trim3 *)M.trims;
     const Node3 *__restrict__ nodes = (const Node3 *)M.nodes;
     const double tol = 4.0 * kPi * M.eps_q;
+    __shared__ NearShared sh;
     double near_sum = 0.0;
     unsigned long long todo = __ballot(act && c > 0);
     while (todo) {
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(64) void k_near3d(LaunchTable T, const int32_t *__r
         for (int k = 0; k < cj; ++k) {
             const int leaf = uniform_i(-1 - nodes[list[k]].right);
             bool budget = false;   // a panel or piece missed its share of 4 pi eps_q
-            double v = near3d<COUNT>(wv, c_quad, prims + leaf, trims, ox, oy, oz, M.eps_on, tol, budget, ctr);
+            double v = near3d<COUNT>(wv, c_quad, prims + leaf, trims, ox, oy, oz, M.eps_on, tol, budget, ctr, sh);
             if (budget) v = NAN;
             if (lane == j) near_sum += v;
         }

@@ -79,6 +79,26 @@ struct FiberWave {
     int shfl_xor(int x, int m) const { return shfl(x, ln ^ m); }
     double bcast(double x, int src) const { return shfl(x, src); }
     int bcast(int x, int src) const { return shfl(x, src); }
+    // the device's order: pairs, quads, half-row mirror, row mirror
+    double sum16(double x) const
+    {
+        x += shfl(x, ln ^ 1);
+        x += shfl(x, ln ^ 2);
+        x += shfl(x, (ln & ~7) | (7 - (ln & 7)));
+        x += shfl(x, (ln & ~15) | (15 - (ln & 15)));
+        return x;
+    }
+    void argmin(double &d, int &k) const
+    {
+        for (int m = 32; m > 0; m >>= 1) {
+            const double od = shfl(d, ln ^ m);
+            const int ok = shfl(k, ln ^ m);
+            if (od < d || (od == d && ok < k)) {
+                d = od;
+                k = ok;
+            }
+        }
+    }
     unsigned long long ballot(bool p) const
     {
         const int par = s->parity[ln];
@@ -109,7 +129,9 @@ void lane_main(int lane)
     FiberWave wv{J->s, lane};
     HostCtr c{};
     bool ovf = false;
-    J->v[lane] = near3d<true>(wv, *J->Q, &J->P, J->tr.data(), J->q[0], J->q[1], J->q[2], J->eps_on, J->tol, ovf, c);
+    NearShared sh;   // the lane's own copy (the lanes run one after another)
+    J->v[lane] =
+        near3d<true>(wv, *J->Q, &J->P, J->tr.data(), J->q[0], J->q[1], J->q[2], J->eps_on, J->tol, ovf, c, sh);
     J->ovf[lane] = ovf;
     J->evals[lane] = c.v[GWN_C_PIECES];
     J->s->done[lane] = true;
