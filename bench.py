@@ -38,6 +38,29 @@ def algorithmic_flops(c: dict, order: int) -> float:
     return float(sum(FLOPS[k] * c[k] for k in FLOPS) + (7 + 8 * order) * c["far"])
 
 
+# Algorithmic FP64 operations per near-field integrand node (3D, k_near3d):
+#   two cubic Bernstein bases with derivatives                  2 x 23 = 46
+#   control net: 16 points x 4 coordinates x 2 (value, v-partial)
+#     multiply-adds, then 4 rows x 4 x 3 accumulations     (128 + 48) x 2 = 352
+#   A = H - q W and its partials                                 9 x 2 = 18
+#   density det[A, A_u, A_v] / |A|^3                                    22
+#   radial map (x, expm1, 1/(1+e), tau, Jacobian, u, v)                 17
+#   f = Jacobian tau density, rounding weight, Kronrod sums             20
+NEAR_FLOPS_PER_NODE = 475
+
+
+def physical_cores():
+    """Physical cores of the host (distinct (core, socket) pairs from
+    lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu", "-p=Core,Socket"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    pairs = {ln.strip() for ln in out.splitlines() if ln.strip() and not ln.startswith("#")}
+    return len(pairs) or None
+
+
 PROFILE = os.path.join(ROOT, "profiles", "k_query2d_svg1024.md")
 KERNEL_SOURCES = ["query.hip", "query_common.h", "gwn_internal.h"]
 
@@ -112,9 +135,40 @@ def bench_small(calls: int = 256) -> dict:
             "back_to_back_queries_per_s": calls * q.shape[0] / dt}
 
 
-def bench3d(steps: int = 1) -> dict:
+def _query3d_timed(G, m, pts):
+    """One timed 3D launch: wall time, per-kernel event times (traversal,
+    near field), and the rows that hit a limit (NaN); the library's report
+    of them, made by the next call on the model, is taken outside the timed
+    region."""
+    import torch
+    out = torch.empty(pts.shape[0], dtype=torch.float64, device=pts.device)
+    ins = torch.empty(pts.shape[0], dtype=torch.uint8, device=pts.device)
+    torch.cuda.synchronize()
+    G.gwn_profile(True)
+    t = time.perf_counter()
+    G.gwn_query(m.h, pts, out, ins)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    G.gwn_profile(False)
+    trav = G.gwn_profile_kernel(G.GWN_K_TRAV3D)[0]
+    near = G.gwn_profile_kernel(G.GWN_K_NEAR3D)[0]
+    w = out.cpu().numpy()
+    flagged = int(np.isnan(w).sum())
+    if flagged:
+        try:
+            G.gwn_query(m.h, pts[:0], out[:0], ins[:0])
+        except G.GwnError:
+            pass
+    return dt, trav, near, w, ins.cpu().numpy(), flagged
+
+
+def bench3d() -> dict:
     """3D side measurement: the bodies scene (4096 trimmed bicubic patches)
-    on its 128^3 grid, FP64 and mixed forms, one timed pass each."""
+    on its 128^3 grid and the CAD assembly (19,968 patches, every one
+    trimmed) with its 1M queries, FP64 and mixed forms, one timed launch
+    each, with the per-kernel split and, for the CAD assembly, the accuracy
+    on the 1,024 rows of the committed oracle fixture.  The near-field
+    kernel's roofline comes from the evaluation counter of the bodies grid."""
     import torch
     from paper_2605_19200_amd import gwn as G
     from paper_2605_19200_amd import presets
@@ -126,16 +180,49 @@ def bench3d(steps: int = 1) -> dict:
     for name, pre in [("fp64", presets.FP64_3D), ("mixed", presets.MIXED_3D)]:
         m = G.Model(P, presets.params(pre))
         m.query(pts[:4096])
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            m.query(pts)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / steps
+        dt, trav, near, _, _, flagged = _query3d_timed(G, m, pts)
         out[name] = {"queries_per_s": q.shape[0] / dt, "ms": dt * 1e3, "beta": pre["beta"],
+                     "k_trav3d_ms": trav, "k_near3d_ms": near, "flagged_rows": flagged,
                      "leaves": int(m.inspect(G.GWN_I_SUMMARY)[0][2]), "resident_bytes": int(m.bytes()[0])}
+        if name == "fp64":
+            c = m.counters(pts)
+            flops = c["pieces"] * NEAR_FLOPS_PER_NODE
+            tf = flops / (near / 1e3) / 1e12
+            out["roofline_k_near3d"] = {
+                "bound": "alu", "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_near3d<false, false>",
+                "kernel_ms": near, "integrand_nodes": int(c["pieces"]), "flops_per_node": NEAR_FLOPS_PER_NODE,
+                "flops_per_launch": float(flops)}
         m.close()
-        print(f"[bench] 3D {name}: {dt * 1e3:.1f} ms per grid", file=sys.stderr, flush=True)
+        print(f"[bench] 3D bodies {name}: {dt * 1e3:.1f} ms per grid (traversal {trav:.1f} ms, near field "
+              f"{near:.1f} ms)", file=sys.stderr, flush=True)
+    # the CAD assembly, config 4
+    P4, q4 = W.config4()
+    pts4 = torch.from_numpy(q4).cuda()
+    fx = os.path.join(ROOT, "tests", "golden", "oracle_cad_assembly_1m.txt")
+    rows, ref = None, None
+    if os.path.exists(fx):
+        data = np.loadtxt(fx, comments="#")
+        rows, ref = data[:, 0].astype(np.int64), data[:, 4]
+    cad = {"workload": f"CAD assembly: 39 bodies, {P4.n} trimmed rational bicubic patches (2-4 trim loops "
+                       "each), 500k near-surface + 500k uniform queries", "queries": q4.shape[0]}
+    for name, pre in [("fp64", presets.FP64_3D), ("mixed", presets.MIXED_3D)]:
+        m = G.Model(P4, presets.params(pre))
+        m.query(pts4[:4096])
+        dt, trav, near, w, ins, flagged = _query3d_timed(G, m, pts4)
+        r = {"queries_per_s": q4.shape[0] / dt, "ms": dt * 1e3, "k_trav3d_ms": trav, "k_near3d_ms": near,
+             "flagged_rows": flagged, "leaves": int(m.inspect(G.GWN_I_SUMMARY)[0][2])}
+        if rows is not None:
+            err = np.abs(w[rows] - ref)
+            sure = np.abs(ref - 0.5) > 1e-3
+            r.update({"oracle_rows": int(rows.size), "max_abs_dw": float(np.nanmax(err)),
+                      "p99_abs_dw": float(np.nanquantile(err, 0.99)),
+                      "containment_mismatch_outside_1e-3": int(np.sum(((ins[rows] != 0) != (ref >= 0.5)) & sure))})
+        cad[name] = r
+        m.close()
+        print(f"[bench] 3D CAD {name}: {dt * 1e3:.1f} ms per 1M queries (traversal {trav:.1f} ms, near field "
+              f"{near:.1f} ms), {flagged} flagged rows", file=sys.stderr, flush=True)
+    out["cad_assembly"] = cad
     return out
 
 
@@ -200,7 +287,7 @@ def served_benchmark(seed: int = 5, n_requests: int = 400, loads=(0.5, 0.8, 0.95
                        f"{n_requests} requests, Poisson arrivals",
            "resident_bytes": srv.resident_bytes(), "build_s": round(build_s, 2), "queries": int(sizes.sum()),
            "saturation": {"requests_per_s": sat_rate, "queries_per_s": sat["queries_per_s"],
-                          "launches": sat["launches"]},
+                          "launches": sat["launches"], "overflow_reports": sat["overflow_reports"]},
            "loads": []}
     for f in loads:
         r = srv.run(mk(f * sat_rate), progress=say)
@@ -333,7 +420,9 @@ def main():
     mismm = int(np.sum(((wm[acc_idx] >= 0.5) != (ref >= 0.5)) & sure))
 
     served = None if args.no_served else served_benchmark()
-    served_all = None if args.no_served else served_benchmark(n_requests=200, kinds=("2d", "3d"), exp3d=(3.0, 4.0))
+    # the serving workload with 2D and 3D models, 3D requests of 10^U(3, 6)
+    # queries like the 2D ones (400 requests)
+    served_all = None if args.no_served else served_benchmark(n_requests=400, kinds=("2d", "3d"), exp3d=(3.0, 6.0))
     side3d = None if args.no_3d else bench3d()
     small = bench_small()
     print(f"[bench] star loop: {small['call_ms_median']:.3f} ms per call, "
@@ -341,16 +430,34 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        # the oracle on the host's physical cores (lscpu), within the CPU
+        # share this process may use; also 1 thread, and 14 threads as in the
+        # paper's measurements
         rate = len(acc_idx) / t_o
-        m_cpu = args.cpu_sample or int(min(max(15.0 * rate, 256), 1 << 20))
-        cidx = rng.permutation(n)[:m_cpu]
-        threads = oracle.max_threads()
-        tc = time.perf_counter()
-        oracle.gwn2d(curves, q[cidx], threads=threads)
-        tc = time.perf_counter() - tc
+        phys = physical_cores()
+        avail = len(os.sched_getaffinity(0))
+        if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+            avail = min(avail, int(os.environ["OMP_NUM_THREADS"]))
+        threads = max(1, min(phys or avail, avail))
+
+        def leg(nthreads, seconds):
+            m_cpu = args.cpu_sample or int(min(max(seconds * rate * nthreads / max(oracle.max_threads(), 1), 64),
+                                               1 << 20))
+            cidx = rng.permutation(n)[:m_cpu]
+            tc = time.perf_counter()
+            oracle.gwn2d(curves, q[cidx], threads=nthreads)
+            tc = time.perf_counter() - tc
+            return m_cpu, tc
+
+        m_cpu, tc = leg(threads, 15.0)
+        m1, t1c = leg(1, 5.0)
+        m14, t14 = leg(14, 5.0)
         cpu = {"value": m_cpu / tc, "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "physical_cores_lscpu": phys,
                "sample": f"{m_cpu} seeded queries of the 1024x1024 grid, direct FP64 sum over all {curves.n} "
-                         f"curves, OpenMP {threads} threads, {tc:.1f} s"}
+                         f"curves, OpenMP {threads} threads, {tc:.1f} s",
+               "threads_1": {"value": m1 / t1c, "sample": f"{m1} queries, {t1c:.1f} s"},
+               "threads_14": {"value": m14 / t14, "sample": f"{m14} queries, {t14:.1f} s"}}
 
     line = {
         "metric": "GWN containment queries/sec at |dw|<=1e-6 (FP64) vs mixed; p50/p99 served latency",

@@ -340,11 +340,16 @@ enum { GWN_I_SUMMARY = 0, GWN_I_LEAVES = 1, GWN_I_NODES = 2, GWN_I_MOMENTS = 3, 
 gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64_t capacity, int64_t *count);
 
 /* Kernel timing.  gwn_profile(1, NULL, NULL) starts recording a pair of HIP
- * events around every traversal-kernel launch (on the stream the kernel runs
- * on); gwn_profile(0, &ms, &launches) waits for the recorded events, returns
- * the summed traversal-kernel time in milliseconds and the number of
- * launches, and stops recording.  Process-wide; not for concurrent use. */
+ * events around every launch of the query kernels (on the stream the kernel
+ * runs on): the 2D query kernel, and the 3D traversal and near-field
+ * kernels, each timed on its own.  gwn_profile(0, &ms, &launches) waits for
+ * the recorded events, returns the summed time in milliseconds and the
+ * number of timed launches, and stops recording.  gwn_profile_kernel then
+ * returns the same sums for one kernel of that set (GWN_K_*; GWN_EINVAL for
+ * another value).  Process-wide; not for concurrent use. */
+enum { GWN_K_QUERY2D = 0, GWN_K_TRAV3D = 1, GWN_K_NEAR3D = 2 };
 gwn_status gwn_profile(int32_t enable, double *total_ms, int64_t *launches);
+gwn_status gwn_profile_kernel(int32_t kernel, double *ms, int64_t *launches);
 
 /* Release a handle (host and device memory).  NULL is accepted. */
 gwn_status gwn_free(gwn_handle h);

@@ -694,4 +694,10 @@ extern "C" gwn_status gwn_profile(int32_t enable, double *total_ms, int64_t *lau
     return profile_control(enable, total_ms, launches);
 }
 
+extern "C" gwn_status gwn_profile_kernel(int32_t kernel, double *ms, int64_t *launches)
+{
+    if (profile_kernel(kernel, ms, launches)) return fail(GWN_EINVAL, "kernel must be GWN_K_QUERY2D, GWN_K_TRAV3D or GWN_K_NEAR3D");
+    return GWN_OK;
+}
+
 extern "C" const char *gwn_last_error(void) { return g_err.c_str(); }

@@ -292,5 +292,10 @@ gwn_status launch_queries(const std::vector<Segment> &segs, int dim, const doubl
 gwn_status query_scratch_bytes(int dim, int64_t n, int32_t n_seg, int64_t &bytes, std::string &err);
 // This device's fixed scratch array (address looked up once per device).
 gwn_status noalloc_scratch(ExtScratch &out, std::string &err);
+// Kernel timing (query.hip): per-kernel sums of the last collected set of
+// recorded launches (gwn_profile, gwn_profile_kernel).
+constexpr int kProfKernels = 3;   // GWN_K_QUERY2D, GWN_K_TRAV3D, GWN_K_NEAR3D
+gwn_status profile_control(int enable, double *total_ms, int64_t *launches);
+gwn_status profile_kernel(int kernel, double *ms, int64_t *launches);
 
 }  // namespace gwn

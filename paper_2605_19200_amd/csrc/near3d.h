@@ -56,7 +56,7 @@ constexpr int kGKo = 2 * kOuterN + 1;      // Kronrod nodes per outer panel
 constexpr int kGKr = 2 * kRadialN + 1;     // Kronrod nodes per radial piece
 constexpr int kMaxPanelsSide = 40;
 constexpr int kOuterLevels = 5;    // an outer panel is refined into at most 32
-constexpr int kRadialLevels = 4;   // a radial piece into at most 16
+constexpr int kRadialLevels = 5;   // a radial piece into at most 32
 
 // Gauss-Kronrod nodes and weights on [0, 1] of the outer and radial pairs
 // (increasing; the odd ones are the Gauss nodes, g* their Gauss weights).
@@ -770,54 +770,28 @@ GWN_HD inline double curve_contribution(const Wv &wv, const QuadTables &Q, const
     return total;
 }
 
-// Start grid of the foot-point search: kFootGrid^2 samples of the square.
-constexpr int kFootGrid = 9;
+// Start grid of the foot-point search: kFootGrid^2 samples of the square,
+// kFootRounds rounds of 64 lanes.  The second start is the best sample
+// outside the first's neighbourhood of +-kFootExcl samples (+-1/4).
+constexpr int kFootGrid = 17;
+constexpr int kFootRounds = (kFootGrid * kFootGrid + 63) / 64;
+constexpr int kFootExcl = (kFootGrid - 1) / 4;
 constexpr double kFootStep = 1.0 / (kFootGrid - 1);
 
-// Foot point of q on the untrimmed patch: the best of kFootGrid^2 samples
-// and the best one outside its 5 x 5 neighbourhood (the distance can have
-// several local minima on strongly non-uniform or folded patches), each
-// refined by projected Gauss-Newton steps, the step halved up to 7 times
-// until the distance falls.  Lanes 0-31 refine the first start, lanes 32-63
-// the second; the line search tries its 8 step lengths on 8 lanes at once
-// and takes the longest that lowers the distance.
-// Returns the squared distance and (bu, bv) the parameters; (ou, ov, od)
-// the other converged minimum (possibly the same point).
+// Projected Gauss-Newton refinement of two starts at once: lanes 0-31
+// refine start 0 within the rectangle rect[0] = (u0, u1, v0, v1), lanes
+// 32-63 start 1 within rect[1]; the step is halved up to 7 times until the
+// distance falls, the 8 step lengths tried on 8 lanes at once (the longest
+// that lowers the distance is taken).  u, v, d (squared distance) are the
+// starts on entry and the results on return, the same on every lane.
 template <class Wv>
-GWN_HD inline double foot_point3d(const Wv &wv, const double *__restrict__ h, double qx, double qy, double qz,
-                                  double &bu, double &bv, double &ou, double &ov, double &od)
+GWN_HD inline void gauss_newton2(const Wv &wv, const double *__restrict__ h, double qx, double qy, double qz,
+                                 double u2[2], double v2[2], double d2[2], const double rect[2][4])
 {
     const int ln = wv.lane();
-    constexpr int NS = kFootGrid * kFootGrid;
-    double dk[2] = {INFINITY, INFINITY};
-#pragma unroll 1
-    for (int r = 0; r < 2; ++r) {
-        const int k = ln + 64 * r;
-        if (k < NS) {
-            const int i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
-            HomEval e;
-            hom_eval(h, kFootStep * i, kFootStep * j, qx, qy, qz, e);
-            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
-            dk[r] = d2 < INFINITY ? d2 : INFINITY;
-        }
-    }
-    double d1 = dk[0];
-    int k1 = ln;
-    if (dk[1] < d1) { d1 = dk[1]; k1 = ln + 64; }
-    argmin64(wv, d1, k1);
-    const int i1 = k1 / kFootGrid, j1 = k1 - kFootGrid * (k1 / kFootGrid);
-    auto outside = [&](int k) {
-        const int i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
-        return abs(i - i1) > 2 || abs(j - j1) > 2;
-    };
-    double d2b = outside(ln) ? dk[0] : INFINITY;
-    int k2 = ln;
-    if (outside(ln + 64) && dk[1] < d2b) { d2b = dk[1]; k2 = ln + 64; }
-    argmin64(wv, d2b, k2);
-    const int i2 = k2 / kFootGrid, j2 = k2 - kFootGrid * (k2 / kFootGrid);
     const int half = ln >> 5, hl = ln & 31;
-    double u = half ? kFootStep * i2 : kFootStep * i1, v = half ? kFootStep * j2 : kFootStep * j1;
-    double d = half ? d2b : d1;
+    double u = u2[half], v = v2[half], d = d2[half];
+    const double lu = rect[half][0], hu = rect[half][1], lv = rect[half][2], hv = rect[half][3];
     bool active = d < INFINITY;
 #pragma unroll 1
     for (int it = 0; it < 16; ++it) {
@@ -839,8 +813,8 @@ GWN_HD inline double foot_point3d(const Wv &wv, const double *__restrict__ h, do
         bool ok = false;
         if (active && hl < 8) {
             const double step = 1.0 / (1 << hl);
-            nu = fmin(1.0, fmax(0.0, u + step * du));
-            nv = fmin(1.0, fmax(0.0, v + step * dv));
+            nu = fmin(hu, fmax(lu, u + step * du));
+            nv = fmin(hv, fmax(lv, v + step * dv));
             HomEval f;
             hom_eval(h, nu, nv, qx, qy, qz, f);
             nd = (f.A[0] * f.A[0] + f.A[1] * f.A[1] + f.A[2] * f.A[2]) / (f.W * f.W);
@@ -860,15 +834,98 @@ GWN_HD inline double foot_point3d(const Wv &wv, const double *__restrict__ h, do
             }
         }
     }
-    const double u1 = wv.bcast(u, 0), v1 = wv.bcast(v, 0), e1 = wv.bcast(d, 0);
-    const double u2 = wv.bcast(u, 32), v2 = wv.bcast(v, 32), e2 = wv.bcast(d, 32);
-    bu = u1;
-    bv = v1;
-    ou = u2;
-    ov = v2;
-    od = e2;
-    if (e2 < e1) { bu = u2; bv = v2; ou = u1; ov = v1; od = e1; return e2; }
-    return e1;
+    for (int k = 0; k < 2; ++k) {
+        u2[k] = wv.bcast(u, 32 * k);
+        v2[k] = wv.bcast(v, 32 * k);
+        d2[k] = wv.bcast(d, 32 * k);
+    }
+}
+
+// Best of kFootGrid^2 samples of the rectangle rect = (u0, u1, v0, v1) for
+// the point nearest q: its parameters and squared distance, the same on
+// every lane.
+template <class Wv>
+GWN_HD inline void best_sample(const Wv &wv, const double *__restrict__ h, double qx, double qy, double qz,
+                               const double rect[4], double &u, double &v, double &d)
+{
+    const int ln = wv.lane();
+    constexpr int NS = kFootGrid * kFootGrid;
+    double bd = INFINITY;
+    int bk = ln;
+#pragma unroll 1
+    for (int r = 0; r < kFootRounds; ++r) {
+        const int k = ln + 64 * r;
+        if (k < NS) {
+            const int i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
+            HomEval e;
+            hom_eval(h, rect[0] + (rect[1] - rect[0]) * (kFootStep * i), rect[2] + (rect[3] - rect[2]) * (kFootStep * j),
+                     qx, qy, qz, e);
+            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
+            if (d2 < bd) { bd = d2; bk = k; }
+        }
+    }
+    argmin64(wv, bd, bk);
+    const int i = bk / kFootGrid, j = bk - kFootGrid * (bk / kFootGrid);
+    u = rect[0] + (rect[1] - rect[0]) * (kFootStep * i);
+    v = rect[2] + (rect[3] - rect[2]) * (kFootStep * j);
+    d = bd;
+}
+
+// Foot point of q on the untrimmed patch: the best of kFootGrid^2 samples
+// and the best one outside its neighbourhood (the distance can have several
+// local minima on strongly non-uniform or folded patches), both refined by
+// gauss_newton2 over the whole square.
+// Returns the squared distance and (bu, bv) the parameters; (ou, ov, od)
+// the other converged minimum (possibly the same point).
+template <class Wv>
+GWN_HD inline double foot_point3d(const Wv &wv, const double *__restrict__ h, double qx, double qy, double qz,
+                                  double &bu, double &bv, double &ou, double &ov, double &od)
+{
+    const int ln = wv.lane();
+    constexpr int NS = kFootGrid * kFootGrid;
+    double dk[kFootRounds];
+#pragma unroll
+    for (int r = 0; r < kFootRounds; ++r) dk[r] = INFINITY;
+#pragma unroll 1
+    for (int r = 0; r < kFootRounds; ++r) {
+        const int k = ln + 64 * r;
+        if (k < NS) {
+            const int i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
+            HomEval e;
+            hom_eval(h, kFootStep * i, kFootStep * j, qx, qy, qz, e);
+            const double d2 = (e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2]) / (e.W * e.W);
+#pragma unroll
+            for (int t = 0; t < kFootRounds; ++t)
+                if (t == r) dk[t] = d2 < INFINITY ? d2 : INFINITY;
+        }
+    }
+    // best sample (the first in grid order on ties)
+    double d1 = INFINITY;
+    int k1 = ln;
+#pragma unroll
+    for (int r = 0; r < kFootRounds; ++r)
+        if (dk[r] < d1) { d1 = dk[r]; k1 = ln + 64 * r; }
+    argmin64(wv, d1, k1);
+    const int i1 = k1 / kFootGrid, j1 = k1 - kFootGrid * (k1 / kFootGrid);
+    double d2b = INFINITY;
+    int k2 = ln;
+#pragma unroll
+    for (int r = 0; r < kFootRounds; ++r) {
+        const int k = ln + 64 * r, i = k / kFootGrid, j = k - kFootGrid * (k / kFootGrid);
+        if ((abs(i - i1) > kFootExcl || abs(j - j1) > kFootExcl) && dk[r] < d2b) { d2b = dk[r]; k2 = k; }
+    }
+    argmin64(wv, d2b, k2);
+    const int i2 = k2 / kFootGrid, j2 = k2 - kFootGrid * (k2 / kFootGrid);
+    double u[2] = {kFootStep * i1, kFootStep * i2}, v[2] = {kFootStep * j1, kFootStep * j2}, d[2] = {d1, d2b};
+    const double sq[2][4] = {{0.0, 1.0, 0.0, 1.0}, {0.0, 1.0, 0.0, 1.0}};
+    gauss_newton2(wv, h, qx, qy, qz, u, v, d, sq);
+    bu = u[0];
+    bv = v[0];
+    ou = u[1];
+    ov = v[1];
+    od = d[1];
+    if (d[1] < d[0]) { bu = u[1]; bv = v[1]; ou = u[0]; ov = v[0]; od = d[0]; return d[1]; }
+    return d[0];
 }
 
 // Polar frame at the foot point (cu, cv) with squared distance d2.
@@ -1034,19 +1091,31 @@ GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__re
             }
             continue;
         }
+        // Two near-singular peaks are resolved apart when the second minimum
+        // is no farther from q than twice the minima's separation in space,
+        // or when the minima lie far apart in parameter space compared with
+        // the peaks' widths there (distance / largest singular value of the
+        // Jacobian): a fold brings distant parameters close to q.
         bool split = false;
         if (fabs(ou - bu) + fabs(ov - bv) > 0.05 && od < INFINITY) {
-            double p[3] = {0.0, 0.0, 0.0}, sep2 = 0.0;
+            double p[3] = {0.0, 0.0, 0.0}, sep2 = 0.0, width = 0.0;
 #pragma unroll 1
             for (int k = 0; k < 2; ++k) {
                 HomEval e;
+                double r[3], Su[3], Sv[3];
                 hom_eval(h, k ? ou : bu, k ? ov : bv, qx, qy, qz, e);
+                euclid(e, r, Su, Sv);
                 for (int a = 0; a < 3; ++a) {
-                    const double x = e.A[a] / e.W;
-                    if (k) sep2 += (x - p[a]) * (x - p[a]); else p[a] = x;
+                    if (k) sep2 += (r[a] - p[a]) * (r[a] - p[a]); else p[a] = r[a];
                 }
+                const double ga = Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2];
+                const double gb = Su[0] * Sv[0] + Su[1] * Sv[1] + Su[2] * Sv[2];
+                const double gc = Sv[0] * Sv[0] + Sv[1] * Sv[1] + Sv[2] * Sv[2];
+                const double l2 = 0.5 * (ga + gc) + sqrt(fmax(0.25 * (ga - gc) * (ga - gc) + gb * gb, 0.0));
+                if (l2 > 0.0) width = fmax(width, sqrt(k ? od : bd) / sqrt(l2));
             }
-            split = od < 4.0 * sep2;
+            const double psep = sqrt((ou - bu) * (ou - bu) + (ov - bv) * (ov - bv));
+            split = od < 4.0 * sep2 || psep > 8.0 * width;
         }
         // cut across the larger parameter gap, halfway between the minima
         const bool cut_u = fabs(ou - bu) >= fabs(ov - bv);
@@ -1097,19 +1166,35 @@ GWN_HD inline double near3d(const Wv &wv, const QuadTables &Q, const Prim3 *__re
         // leaf is split, and the stretches of the cut line.
         const int nparts = split ? 2 : 1;
         const int ncurves = nt == 0 ? 4 : split ? 3 * nt + ncr / 2 : nt;
+        // each part is integrated about its own foot point, the point of the
+        // part's rectangle nearest q: the best of a sample grid of the
+        // rectangle or the part's minimum, refined within the rectangle (the
+        // nearest point of a part may lie on the cut, and the part's minimum
+        // may be a constrained one on the square's edge)
+        double pu[2] = {bu, ou}, pv[2] = {bv, ov}, pd[2] = {bd, od};
+        bool lows[2] = {true, true};
+        double prect[2][4] = {{0.0, 1.0, 0.0, 1.0}, {0.0, 1.0, 0.0, 1.0}};
+        if (split) {
+#pragma unroll 1
+            for (int part = 0; part < 2; ++part) {
+                lows[part] = (cut_u ? pu[part] : pv[part]) < cut;
+                if (cut_u) prect[part][lows[part] ? 1 : 0] = cut;
+                else prect[part][lows[part] ? 3 : 2] = cut;
+                double su, sv, sd;
+                best_sample(wv, h, qx, qy, qz, prect[part], su, sv, sd);
+                if (sd < pd[part]) { pu[part] = su; pv[part] = sv; pd[part] = sd; }
+            }
+            gauss_newton2(wv, h, qx, qy, qz, pu, pv, pd, prect);
+        }
         Budget B{tol, 0, 0};
         double total = 0.0;
 #pragma unroll 1
         for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll 1
             for (int part = 0; part < nparts; ++part) {
-                const double cu = part ? ou : bu, cv = part ? ov : bv, d2 = part ? od : bd;
-                double u0 = 0.0, u1 = 1.0, v0 = 0.0, v1 = 1.0;
-                const bool low = (cut_u ? cu : cv) < cut;
-                if (split) {
-                    if (cut_u) { if (low) u1 = cut; else u0 = cut; }
-                    else { if (low) v1 = cut; else v0 = cut; }
-                }
+                const double cu = pu[part], cv = pv[part], d2 = pd[part];
+                const double u0 = prect[part][0], u1 = prect[part][1], v0 = prect[part][2], v1 = prect[part][3];
+                const bool low = lows[part];
                 sh.fr = near_frame(h, cu, cv, d2, qx, qy, qz, eps_on);
                 compiler_fence();
                 const NearFrame &fr = sh.fr;

@@ -514,9 +514,15 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
 // ---------------------------------------------------------------------------
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
-static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+struct ProfEvents {
+    int kernel;
+    hipEvent_t a, b;
+};
+static std::vector<ProfEvents> g_prof_events;
+static double g_prof_ms[kProfKernels];
+static int64_t g_prof_n[kProfKernels];
 
-static void prof_begin(hipStream_t s, hipEvent_t &a)
+void prof_begin(hipStream_t s, hipEvent_t &a)
 {
     a = nullptr;
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -525,14 +531,14 @@ static void prof_begin(hipStream_t s, hipEvent_t &a)
     (void)hipEventRecord(a, s);
 }
 
-static void prof_end(hipStream_t s, hipEvent_t a)
+void prof_end(hipStream_t s, hipEvent_t a, int kernel)
 {
     if (!a) return;
     hipEvent_t b = nullptr;
     if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
     (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof_events.emplace_back(a, b);
+    g_prof_events.push_back({kernel, a, b});
 }
 
 gwn_status profile_control(int enable, double *total_ms, int64_t *launches)
@@ -540,19 +546,34 @@ gwn_status profile_control(int enable, double *total_ms, int64_t *launches)
     std::lock_guard<std::mutex> lk(g_prof_mu);
     double ms = 0.0;
     int64_t cnt = 0;
+    for (int k = 0; k < kProfKernels; ++k) {
+        g_prof_ms[k] = 0.0;
+        g_prof_n[k] = 0;
+    }
     for (auto &ev : g_prof_events) {
         float t = 0.f;
-        if (hipEventSynchronize(ev.second) == hipSuccess && hipEventElapsedTime(&t, ev.first, ev.second) == hipSuccess) {
+        if (hipEventSynchronize(ev.b) == hipSuccess && hipEventElapsedTime(&t, ev.a, ev.b) == hipSuccess) {
             ms += t;
             ++cnt;
+            g_prof_ms[ev.kernel] += t;
+            g_prof_n[ev.kernel] += 1;
         }
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
     }
     g_prof_events.clear();
     g_prof_on = enable != 0;
     if (total_ms) *total_ms = ms;
     if (launches) *launches = cnt;
+    return GWN_OK;
+}
+
+gwn_status profile_kernel(int kernel, double *ms, int64_t *launches)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (kernel < 0 || kernel >= kProfKernels) return GWN_EINVAL;
+    if (ms) *ms = g_prof_ms[kernel];
+    if (launches) *launches = g_prof_n[kernel];
     return GWN_OK;
 }
 static gwn_status hip_err(hipError_t e, const char *what, std::string &err)
@@ -676,9 +697,9 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
                                                stream);
     if (e != hipSuccess) st = hip_err(e, "key/sort launch", err);
     if (!st) {
-        hipEvent_t ev0;
-        prof_begin(stream, ev0);
         if (dim == 2) {
+            hipEvent_t ev0;
+            prof_begin(stream, ev0);
             const int grid_w = (T.n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
             bool any_mixed = false;
             for (int j = 0; j < T.n_seg; ++j) any_mixed |= T.models[T.seg_model[j]].precision == GWN_MIXED;
@@ -700,10 +721,10 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
             }
             e = hipGetLastError();
             if (e != hipSuccess) st = hip_err(e, "query launch", err);
+            prof_end(stream, ev0, GWN_K_QUERY2D);
         } else {
             st = launch_query3d(T, pts, v_out, ow, oi, (long long *)counters, near_buf, P.near, stream, err);
         }
-        prof_end(stream, ev0);
     }
     if (!ext.ptr) {
         hipError_t e2 = hipFreeAsync(buf, stream);

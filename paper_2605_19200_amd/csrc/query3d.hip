@@ -317,42 +317,41 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     flush_counters<COUNT>(ctr, counters);
 }
 
-// Pass 2 (3D): the near-field leaves of one wave's queries.  The wave takes
-// their (query, leaf) pairs one at a time, query by query in the
+// Pass 2 (3D): the near-field leaves of one query, in a workgroup of one
+// wave.  The wave takes the query's (query, leaf) pairs one at a time in the
 // traversal's order, and all 64 lanes evaluate each pair together (the
 // rule's integrand evaluations are shared out over the lanes, its control
-// is the same on all of them).  Each query adds its pairs' values one by
-// one in that order, so its result does not depend on its wave or batch
-// mates.  Then classification and scatter.  Mixed form, first pass: lanes
-// with |w - 0.5| < band are flagged for the FP64 re-evaluation instead of
+// is the same on all of them); the query adds its pairs' values one by one
+// in that order, so its result does not depend on its batch mates.  Then
+// classification and scatter.  Mixed form, first pass: a query with
+// |w - 0.5| < band is flagged for the FP64 re-evaluation instead of
 // written.
-// One wave per workgroup: the waves' pair counts differ widely, and
-// single-wave workgroups let each SIMD take the next wave as soon as its
-// own is done.  Two waves per SIMD (256 registers each, some spilled) ran
-// the bodies grid 13 % faster than one wave with no spill; four (128
-// registers) were slower again.
+// One query per wave keeps the work of a wave small and even: a query has
+// at most kNearSlots pairs, while the 64 queries of a traversal wave near a
+// surface can hold hundreds of trimmed pairs (one such wave set the launch
+// time on the CAD assembly).  Runs of kXcdRunNear consecutive queries stay
+// on one XCD (neighbouring queries share leaves).  Two waves per SIMD (256
+// registers each, some spilled) ran the bodies grid 13 % faster than one
+// wave with no spill; four (128 registers) were slower again.
+constexpr int kXcdRunNear = 256;
+
 template <bool COUNT, bool RECLASS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_near3d(LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS,
-                                               const double *__restrict__ pts, double *__restrict__ out_w,
-                                               uint8_t *__restrict__ out_in, long long *counters)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_near3d(
+    LaunchTable T, const int32_t *__restrict__ perm, NearScratch NS, const double *__restrict__ pts,
+    double *__restrict__ out_w, uint8_t *__restrict__ out_in, long long *counters)
 {
     const int lane = lane_id();
-    const int wave = xcd_block<kXcdRun3 * kWavesPerBlock>();
+    const int64_t slot = uniform_i(xcd_block<kXcdRunNear>());   // query position in the wave grid
+    const int wave = (int)(slot / T.qpw), j = (int)(slot - (int64_t)wave * T.qpw);
     if (wave >= T.n_waves) return;
     const int s = wave_segment(T, wave);
     const DevModel &M = T.models[T.seg_model[s]];
-    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + lane;
-    // per-query records are indexed by the query's position in the wave
-    // grid (qpw per wave), read and written by valid lanes only
-    const bool valid = lane < T.qpw && pos < T.qoff[s + 1];
-    const int64_t slot = (int64_t)wave * T.qpw + (valid ? lane : 0);
-    const bool act = valid && (!RECLASS || NS.need[slot]);
-    if (!__ballot(act)) return;
-    const int row = act ? perm[pos] : 0;
-    const double qx = act ? pts[3 * (int64_t)row] : 0.0;
-    const double qy = act ? pts[3 * (int64_t)row + 1] : 0.0;
-    const double qz = act ? pts[3 * (int64_t)row + 2] : 0.0;
-    const int full = act ? NS.cnt[slot] : 0;
+    const int64_t pos = T.qoff[s] + (int64_t)(wave - T.woff[s]) * T.qpw + j;
+    if (pos >= T.qoff[s + 1]) return;
+    if (RECLASS && !NS.need[slot]) return;
+    const int row = perm[pos];
+    const double qx = pts[3 * (int64_t)row], qy = pts[3 * (int64_t)row + 1], qz = pts[3 * (int64_t)row + 2];
+    const int full = NS.cnt[slot];
     const int c = min(full, kNearSlots);
     Ctr ctr;
 #pragma unroll
@@ -363,23 +362,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const Node3 *__restrict__ nodes = (const Node3 *)M.nodes;
     const double tol = 4.0 * kPi * M.eps_q;
     __shared__ NearShared sh;
+    const int32_t *__restrict__ list = NS.list + slot * kNearSlots;
     double near_sum = 0.0;
-    unsigned long long todo = __ballot(act && c > 0);
-    while (todo) {
-        const int j = __builtin_ctzll(todo);
-        todo &= todo - 1;
-        const int cj = wv.bcast(c, j);
-        const double ox = wv.bcast(qx, j), oy = wv.bcast(qy, j), oz = wv.bcast(qz, j);
-        const int32_t *__restrict__ list = NS.list + ((int64_t)wave * T.qpw + j) * kNearSlots;
-        for (int k = 0; k < cj; ++k) {
-            const int leaf = uniform_i(-1 - nodes[list[k]].right);
-            bool budget = false;   // a panel or piece missed its share of 4 pi eps_q
-            double v = near3d<COUNT>(wv, c_quad, prims + leaf, trims, ox, oy, oz, M.eps_on, tol, budget, ctr, sh);
-            if (budget) v = NAN;
-            if (lane == j) near_sum += v;
-        }
+    for (int k = 0; k < c; ++k) {
+        const int leaf = uniform_i(-1 - nodes[list[k]].right);
+        bool budget = false;   // a panel or piece missed its share of 4 pi eps_q
+        double v = near3d<COUNT>(wv, c_quad, prims + leaf, trims, qx, qy, qz, M.eps_on, tol, budget, ctr, sh);
+        if (budget) v = NAN;
+        near_sum += v;
     }
-    if (act) {
+    if (lane == 0) {
         double wq = (NS.part[slot] + near_sum) * (1.0 / (4.0 * kPi));
         // more near leaves than slots, or a leaf whose near-field rule could
         // not meet eps_q within its refinement budget (its value is NaN)
@@ -437,7 +429,7 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
     bool any_mixed = false;
     for (int j = 0; j < T.n_seg; ++j) any_mixed |= T.models[T.seg_model[j]].precision == GWN_MIXED;
     const dim3 g(grid), b(kBlock);
-    const dim3 gn(T.n_waves), bn(64);   // k_near3d: one wave per workgroup
+    const dim3 gn((unsigned)((int64_t)T.n_waves * T.qpw)), bn(64);   // k_near3d: one wave per query slot
     if (counters) {
         hipLaunchKernelGGL((k_trav3d<true, false>), g, b, 0, stream, T, pts, perm, NS, counters);
         hipLaunchKernelGGL((k_near3d<true, false>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
@@ -446,12 +438,22 @@ gwn_status launch_query3d(const LaunchTable &T, const double *pts, const int32_t
             hipLaunchKernelGGL((k_near3d<true, true>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
         }
     } else {
+        // each launch timed on its own while kernel timing is on
+        hipEvent_t ev;
+        prof_begin(stream, ev);
         hipLaunchKernelGGL((k_trav3d<false, false>), g, b, 0, stream, T, pts, perm, NS, counters);
+        prof_end(stream, ev, GWN_K_TRAV3D);
+        prof_begin(stream, ev);
         hipLaunchKernelGGL((k_near3d<false, false>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in, counters);
+        prof_end(stream, ev, GWN_K_NEAR3D);
         if (any_mixed) {
+            prof_begin(stream, ev);
             hipLaunchKernelGGL((k_trav3d<false, true>), g, b, 0, stream, T, pts, perm, NS, counters);
+            prof_end(stream, ev, GWN_K_TRAV3D);
+            prof_begin(stream, ev);
             hipLaunchKernelGGL((k_near3d<false, true>), gn, bn, 0, stream, T, perm, NS, pts, out_w, out_in,
                                counters);
+            prof_end(stream, ev, GWN_K_NEAR3D);
         }
     }
     e = hipGetLastError();

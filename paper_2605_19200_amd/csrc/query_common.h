@@ -7,6 +7,11 @@
 
 namespace gwn {
 
+// A pair of events around a launch of one of the timed kernels, on its
+// stream, while recording is on (query.hip).
+void prof_begin(hipStream_t s, hipEvent_t &a);
+void prof_end(hipStream_t s, hipEvent_t a, int kernel);
+
 constexpr int kMaxSeg = 32;
 constexpr int kMaxModels = 8;
 constexpr int kWavesPerBlock = kBlock / 64;

@@ -26,7 +26,8 @@ GWN_NCOUNTERS = len(COUNTER_NAMES)
 EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
             "gwn_get_params", "gwn_query", "gwn_query_noalloc", "gwn_query_scratch_bytes",
             "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
-            "gwn_free", "gwn_last_error"]
+            "gwn_profile_kernel", "gwn_free", "gwn_last_error"]
+GWN_K_QUERY2D, GWN_K_TRAV3D, GWN_K_NEAR3D = 0, 1, 2
 GWN_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 
@@ -90,6 +91,7 @@ def lib():
             ("gwn_inspect", [vp, i32, vp, i64, ctypes.POINTER(i64)]),
             ("gwn_free", [vp]),
             ("gwn_profile", [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+            ("gwn_profile_kernel", [i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -346,10 +348,18 @@ def gwn_inspect(h, what: int) -> np.ndarray:
 
 
 def gwn_profile(enable: bool):
-    """Start (True) or stop (False) traversal-kernel event timing; stopping
+    """Start (True) or stop (False) query-kernel event timing; stopping
     returns (total_ms, launches)."""
     ms, cnt = ctypes.c_double(), ctypes.c_int64()
     _check(lib().gwn_profile(1 if enable else 0, ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def gwn_profile_kernel(kernel: int):
+    """(total_ms, launches) of one kernel (GWN_K_*) in the set collected by
+    the last gwn_profile(False)."""
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().gwn_profile_kernel(int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
 
 

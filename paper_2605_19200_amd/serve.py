@@ -109,6 +109,7 @@ class Server:
         with torch.cuda.device(self.device):
             self.slots = [_Slot(torch.cuda.Stream(device=self.device), torch.cuda.Event()) for _ in range(n_slots)]
         self.launches = 0
+        self.overflow_reports = 0             # launches that reported an earlier launch's NaN queries
         self.in_flight_bytes = 0
         self.peak_bytes = 0
         self.record_timing = record_timing
@@ -262,6 +263,7 @@ class Server:
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else 0.0,
             "mean_ms": float(lat.mean() * 1e3) if lat.size else 0.0,
             "launches": self.launches, "peak_in_flight_bytes": self.peak_bytes, "budget_bytes": self.budget,
+            "overflow_reports": self.overflow_reports,
         }
 
     # -- live producers ---------------------------------------------------------
@@ -390,8 +392,20 @@ class Server:
             d_w = torch.empty(nq, dtype=torch.float64, device=self.device)
             d_in = torch.empty(nq, dtype=torch.uint8, device=self.device)
             d_pts.view(-1).copy_(h_pts, non_blocking=True)
-            G.gwn_query_batch([self.models[m].h for m in seg_models], np.asarray(seg_off, np.int64), d_pts, d_w,
-                              d_in, s.stream)
+            handles = [self.models[m].h for m in seg_models]
+            # A query that hit a traversal or near-field limit comes back NaN
+            # in its own request; the library reports the count on the next
+            # call on that model, which then launches nothing.  Such a report
+            # belongs to an earlier launch: count it and launch again (at most
+            # one report per model of the batch).
+            for attempt in range(len(handles) + 1):
+                try:
+                    G.gwn_query_batch(handles, np.asarray(seg_off, np.int64), d_pts, d_w, d_in, s.stream)
+                    break
+                except G.GwnError as e:
+                    if e.status != G.GWN_EOVERFLOW or attempt == len(handles):
+                        raise
+                    self.overflow_reports += 1
             h_w = self._pinned(s, "w", nq, torch.float64)
             h_in = self._pinned(s, "in", nq, torch.uint8)
             h_w.copy_(d_w, non_blocking=True)

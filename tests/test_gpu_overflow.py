@@ -100,3 +100,28 @@ def test_scratch_bytes_match_pool_usage(kind):
         print(f"scratch {kind} n={n}: library {need} B, pool high-water {used} B", flush=True)
         assert need <= used <= need + (2 << 20), (n, need, used)
     m.close()
+
+
+def test_served_overflow_stays_in_its_request():
+    """The served form: a request with a query that hits the near-field slot
+    budget gets NaN for that query, the report of the count (on the next
+    launch on the model) does not fail the next request, and every other
+    value equals the direct call's."""
+    from paper_2605_19200_amd import serve
+    P = stacked_planes()
+    q_bad = np.array([[0.5, 0.5, 0.0395], [0.3, 0.3, 5.0]])
+    q_ok = np.array([[5.0, 5.0, 5.0], [0.5, 0.5, -3.0], [0.2, 0.7, 2.0]])
+    srv = serve.Server(budget_bytes=64 << 20, n_slots=1)
+    srv.add_model(P, presets.params(presets.FP64_3D, max_diag_frac=0.0))
+    print("served overflow test: stacked planes, two requests", flush=True)
+    fa = srv.submit(0, q_bad)
+    wa, _ = fa.result(timeout=60)
+    fb = srv.submit(0, q_ok)
+    wb, _ = fb.result(timeout=60)
+    srv.close()
+    assert np.isnan(wa[0]) and np.isfinite(wa[1])
+    assert srv.overflow_reports == 1
+    m = G.Model(P, presets.params(presets.FP64_3D, max_diag_frac=0.0))
+    w_ref, _ = run(m, q_ok)
+    assert np.array_equal(wb, w_ref)
+    m.close()
