@@ -421,8 +421,8 @@ def main():
 
     served = None if args.no_served else served_benchmark()
     # the serving workload with 2D and 3D models, 3D requests of 10^U(3, 6)
-    # queries like the 2D ones (400 requests)
-    served_all = None if args.no_served else served_benchmark(n_requests=400, kinds=("2d", "3d"), exp3d=(3.0, 6.0))
+    # queries like the 2D ones (200 requests)
+    served_all = None if args.no_served else served_benchmark(n_requests=200, kinds=("2d", "3d"), exp3d=(3.0, 6.0))
     side3d = None if args.no_3d else bench3d()
     small = bench_small()
     print(f"[bench] star loop: {small['call_ms_median']:.3f} ms per call, "
@@ -440,18 +440,19 @@ def main():
             avail = min(avail, int(os.environ["OMP_NUM_THREADS"]))
         threads = max(1, min(phys or avail, avail))
 
-        def leg(nthreads, seconds):
-            m_cpu = args.cpu_sample or int(min(max(seconds * rate * nthreads / max(oracle.max_threads(), 1), 64),
-                                               1 << 20))
+        def leg(nthreads, m_cpu):
             cidx = rng.permutation(n)[:m_cpu]
             tc = time.perf_counter()
             oracle.gwn2d(curves, q[cidx], threads=nthreads)
             tc = time.perf_counter() - tc
             return m_cpu, tc
 
-        m_cpu, tc = leg(threads, 15.0)
-        m1, t1c = leg(1, 5.0)
-        m14, t14 = leg(14, 5.0)
+        # sample sizes for about 15 s (all cores) and 5 s (1 and 14 threads),
+        # from the accuracy sample's rate and then the first leg's
+        m_cpu, tc = leg(threads, args.cpu_sample or int(min(max(15.0 * rate, 256), 1 << 20)))
+        per_thread = m_cpu / tc / threads
+        m1, t1c = leg(1, int(max(5.0 * per_thread, 64)))
+        m14, t14 = leg(14, int(max(5.0 * per_thread * 14, 64)))
         cpu = {"value": m_cpu / tc, "unit": "queries/s", "cores": threads, "kind": "oracle",
                "physical_cores_lscpu": phys,
                "sample": f"{m_cpu} seeded queries of the 1024x1024 grid, direct FP64 sum over all {curves.n} "
