@@ -6,7 +6,7 @@
 // on the host (tree.cpp), which receives the sorted leaf order and the child
 // links and produces the same tree as a host-only build.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include "radix.h"
 
 #include <algorithm>
 #include <string>
@@ -126,9 +126,7 @@ bool lbvh_device(int device, int dim, int n, const double *lo, const double *hi,
     DevBuf d_lo, d_hi, d_k0, d_k1, d_i0, d_i1, d_cl, d_cr, d_tmp;
     size_t tmp_bytes = 0;
     hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                               (int32_t *)nullptr, (int32_t *)nullptr, n, 0, 64);
+    tmp_bytes = radix_temp_bytes(n);
     if (e == hipSuccess) e = hipMalloc(&d_lo.p, 3 * nb * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&d_hi.p, 3 * nb * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&d_k0.p, nb * sizeof(uint64_t));
@@ -147,19 +145,20 @@ bool lbvh_device(int device, int dim, int n, const double *lo, const double *hi,
         e = hipGetLastError();
     }
     // LSD radix sort: stable, so equal codes keep leaf order, as the host's
-    // stable sort does
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(d_tmp.p, tmp_bytes, (const uint64_t *)d_k0.p, (uint64_t *)d_k1.p,
-                                               (const int32_t *)d_i0.p, (int32_t *)d_i1.p, n, 0, 64);
+    // stable sort does; the sorted pairs end up in buffer `sel`
+    uint64_t *kb[2] = {(uint64_t *)d_k0.p, (uint64_t *)d_k1.p};
+    int32_t *ib[2] = {(int32_t *)d_i0.p, (int32_t *)d_i1.p};
+    int sel = 0;
+    if (e == hipSuccess) e = radix_sort_pairs(kb, ib, n, 0, 64, d_tmp.p, 0, sel);
     if (e == hipSuccess && n > 1) {
-        hipLaunchKernelGGL(k_karras, grid, block, 0, 0, (const uint64_t *)d_k1.p, n, (int32_t *)d_cl.p,
+        hipLaunchKernelGGL(k_karras, grid, block, 0, 0, (const uint64_t *)kb[sel], n, (int32_t *)d_cl.p,
                            (int32_t *)d_cr.p);
         e = hipGetLastError();
     }
     order.assign(nb, 0);
     cl.assign(nb > 1 ? nb - 1 : 0, 0);
     cr.assign(nb > 1 ? nb - 1 : 0, 0);
-    if (e == hipSuccess) e = hipMemcpy(order.data(), d_i1.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(order.data(), ib[sel], nb * sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e == hipSuccess && n > 1) e = hipMemcpy(cl.data(), d_cl.p, (nb - 1) * sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e == hipSuccess && n > 1) e = hipMemcpy(cr.data(), d_cr.p, (nb - 1) * sizeof(int32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) {

@@ -14,14 +14,15 @@
 // same order, so every result is bitwise independent of its wave mates.
 // Node records are read at wave-uniform addresses (scalar loads).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <utility>
 #include <vector>
 
+#include "radix.h"
 #include "gwn_internal.h"
 #include "query_common.h"
 
@@ -598,10 +599,13 @@ static int32_t queries_per_wave(int64_t n)
 // Scratch of one launch chunk, in one buffer with 256-byte aligned parts:
 // sort keys and row indices (double-buffered), the radix sort's temporary
 // storage and, in 3D, the near-field pass's per-slot records.  Nothing in it
-// needs to start at zero: every record is written before it is read.  A
-// small launch sorts on the top 24 key bits only (segment and the coarse
-// Morton levels, far finer than its waves): fewer radix passes and no effect
-// on any value.
+// needs to start at zero: every record is written before it is read.  The
+// sort orders the queries for coherent waves only (no value depends on the
+// order), so it takes the top 24 Morton bits (bits 24-47: 2^12 cells per
+// axis in 2D, 2^8 in 3D, far finer than a wave's footprint), or the top 18
+// for a launch under 2^16 queries, and the segment bits 48-53 only when the
+// launch has more than one segment: three 8-bit radix passes for one
+// segment instead of seven.
 struct ScratchPlan {
     size_t keys = 0, vals = 0, temp = 0, temp_bytes = 0;
     NearBytes near;
@@ -613,11 +617,9 @@ static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 static hipError_t plan_scratch(int dim, int64_t n, int64_t slots, hipStream_t stream, ScratchPlan &P)
 {
-    P.sort_lo = n < (1 << 16) ? 30 : 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, P.temp_bytes, (uint64_t *)nullptr,
-                                                      (uint64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
-                                                      (int)n, P.sort_lo, 54, stream);
-    if (e != hipSuccess) return e;
+    P.sort_lo = n < (1 << 16) ? 30 : 24;
+    P.temp_bytes = radix_temp_bytes(n);
+    (void)stream;
     P.keys = al256(sizeof(uint64_t) * n);
     P.vals = al256(sizeof(int32_t) * n);
     P.temp = al256(P.temp_bytes);
@@ -692,9 +694,15 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
     gwn_status st = GWN_OK;
     hipLaunchKernelGGL(k_keys, dim3(grid_q), dim3(kBlock), 0, stream, T, dim, pts, k_in, v_in, n);
     e = hipGetLastError();
-    if (e == hipSuccess)
-        e = hipcub::DeviceRadixSort::SortPairs(temp, P.temp_bytes, k_in, k_out, v_in, v_out, (int)n, P.sort_lo, 54,
-                                               stream);
+    // the sorted permutation ends up in one of the two value buffers
+    const int32_t *perm = v_out;
+    if (e == hipSuccess) {
+        uint64_t *kb[2] = {k_in, k_out};
+        int32_t *vb[2] = {v_in, v_out};
+        int sel = 0;
+        e = radix_sort_pairs(kb, vb, n, P.sort_lo, T.n_seg > 1 ? 54 : 48, temp, stream, sel);
+        perm = vb[sel];
+    }
     if (e != hipSuccess) st = hip_err(e, "key/sort launch", err);
     if (!st) {
         if (dim == 2) {
@@ -706,24 +714,24 @@ static gwn_status launch_chunk(const std::vector<Segment> &segs, size_t s0, size
             long long *ctrs = (long long *)counters;
             if (any_mixed) {
                 if (ctrs)
-                    hipLaunchKernelGGL(k_query2d_mixed<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out,
+                    hipLaunchKernelGGL(k_query2d_mixed<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, perm,
                                        ow, oi, ctrs);
                 else
-                    hipLaunchKernelGGL(k_query2d_mixed<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out,
+                    hipLaunchKernelGGL(k_query2d_mixed<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, perm,
                                        ow, oi, ctrs);
             } else {
                 if (ctrs)
-                    hipLaunchKernelGGL(k_query2d<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow, oi,
+                    hipLaunchKernelGGL(k_query2d<true>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, perm, ow, oi,
                                        ctrs);
                 else
-                    hipLaunchKernelGGL(k_query2d<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, v_out, ow,
+                    hipLaunchKernelGGL(k_query2d<false>, dim3(grid_w), dim3(kBlock), 0, stream, T, pts, perm, ow,
                                        oi, ctrs);
             }
             e = hipGetLastError();
             if (e != hipSuccess) st = hip_err(e, "query launch", err);
             prof_end(stream, ev0, GWN_K_QUERY2D);
         } else {
-            st = launch_query3d(T, pts, v_out, ow, oi, (long long *)counters, near_buf, P.near, stream, err);
+            st = launch_query3d(T, pts, perm, ow, oi, (long long *)counters, near_buf, P.near, stream, err);
         }
     }
     if (!ext.ptr) {

@@ -69,6 +69,30 @@ def test_ragged_sizes_bitwise(cfg1):
     torch.cuda.synchronize()
 
 
+def test_sort_sizes_duplicates_and_order(cfg1):
+    """The space-filling-curve sort of a launch (radix tiles of 4096 keys;
+    launches under 2^16 queries sort on the top 24 key bits): at sizes
+    around the tile and the 2^16 boundary, with a third of the points
+    repeated, every query is evaluated exactly once and its value does not
+    depend on the order of the points (a shuffled launch gives the same
+    bits)."""
+    curves, q, _ = cfg1
+    m = G.Model(curves, presets.params(presets.FP64_2D))
+    rng = W.Rng(27, "sort")
+    lo, hi = curves.bbox()
+    for n in [2, 3, 4095, 4096, 4097, 8193, 65535, 65536, 70001]:
+        pts = rng.uniform((n, 2), 0, 1) * (np.asarray(hi) - np.asarray(lo)) * 1.2 + np.asarray(lo) - 0.1 * (
+            np.asarray(hi) - np.asarray(lo))
+        dup = rng.integers(n // 3, 0, n - 1)
+        pts[rng.integers(n // 3, 0, n - 1)] = pts[dup]
+        w, ins = run(m, pts)
+        perm = rng.permutation(n)
+        ws, inss = run(m, pts[perm])
+        assert np.all(np.isfinite(w)), n
+        assert np.array_equal(ws, w[perm]) and np.array_equal(inss, ins[perm]), n
+        print(f"sort check n={n}: ok", flush=True)
+
+
 def test_degenerate_models(oracle):
     q = W.Rng(21, "q").uniform((300, 2), -1.5, 1.5)
     # empty model
