@@ -71,6 +71,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is missing: run __graft_entry__.build() "
                                "(or python paper_2605_19200_amd/build.py)")
+        # PyTorch carries its own HIP runtime; it has to be loaded before the
+        # library's, or torch finds no GPU once the library has initialised
+        # the device (the binding hands the library torch's device memory)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         L.gwn_default_params.argtypes = [ctypes.POINTER(gwn_params)]

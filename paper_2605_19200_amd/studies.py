@@ -1,4 +1,4 @@
-"""Parameter studies of the accelerated 2D query on the synthetic workloads,
+"""Parameter studies of the accelerated query on the synthetic workloads,
 after the paper's experiments on its own datasets:
 
   order_beta     max |dw| and time against (order, beta)      (Sec. 4.2, Fig. beta_sweep)
@@ -11,20 +11,29 @@ after the paper's experiments on its own datasets:
                                                                (Sec. 4.3)
   overlap        k nearly overlapping closed 15-gons: absolute and relative
                  error and misclassifications against k       (Sec. 4.3, Fig. overlap_demo)
+  order_beta_3d  bodies scene (128^3 grid) and CAD assembly (1M queries):
+                 error and time against (order, beta)         (Sec. 4.2)
+  subdivision_3d bodies scene: leaves, build and query time, error against
+                 the subdivision threshold                     (Sec. 4.1)
 
 The order, disagreement and overlap studies use the paper's 10 % subdivision
 threshold and one far-field factor for all clusters; the subdivision study
 runs the FP64 preset (order 12, error-budgeted far test); far_tol sweeps
 the budget of that test.
-The reference is the same engine with the far field switched off (beta =
-1e8: every leaf evaluated directly), whose agreement with the FP64 oracle is
-a GPU test of its own.  Each study prints one JSON line to stdout and its
-progress to stderr.
+Errors are taken against the oracle: every study reports the largest error
+on the seeded rows of its workload whose oracle values are committed under
+tests/golden/ (1,024 per workload; the 3D ones hold half near-surface
+points).  The 2D studies also report the error over the whole grid against
+the same engine with the far field switched off (beta = 1e8: every leaf
+evaluated directly), which a GPU test pins to the oracle rows on this
+drawing.  Each study prints one JSON line to stdout and its progress to
+stderr.
 
     python -m paper_2605_19200_amd.studies [--only NAME ...]
 """
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -44,18 +53,55 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
+def _query(model, qd, out=None, ins=None):
+    """One launch; a report of an earlier launch's NaN (flagged) queries,
+    which launches nothing, is taken and the call made again."""
+    try:
+        return model.query(qd, out, ins)
+    except G.GwnError as e:
+        if e.status != G.GWN_EOVERFLOW:
+            raise
+        return model.query(qd, out, ins)
+
+
 def _run(model, qd, reps=3):
     """Values and median wall time (ms) of `reps` queries after one warm-up."""
     import torch
-    out, ins = model.query(qd)
+    out, ins = _query(model, qd)
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
         t = time.perf_counter()
-        model.query(qd, out, ins)
+        _query(model, qd, out, ins)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t)
     return out.cpu().numpy(), float(np.median(ts) * 1e3)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "tests", "golden")
+
+
+def oracle_rows(name):
+    """(rows, points, w) of a committed oracle fixture (row -1: a point that
+    is not a row of the workload's query array)."""
+    dim, data = 3, []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                if line[1:].strip().startswith("dim:"):
+                    dim = int(line.split(":", 1)[1])
+                continue
+            data.append([float(x) for x in line.split()])
+    d = np.array(data).reshape(-1, dim + 2)
+    return d[:, 0].astype(np.int64), d[:, 1:1 + dim], d[:, 1 + dim]
+
+
+def _oracle_err(model, fx):
+    """max and p99 |dw| of a model against an oracle fixture's rows."""
+    _, pts, ref = fx
+    w, _ = _run(model, _dev(pts), reps=1)
+    err = np.abs(w - ref)
+    return float(np.nanmax(err)), float(np.nanquantile(err, 0.99)), int(np.isnan(w).sum())
 
 
 def _reference(curves, qd):
@@ -68,6 +114,7 @@ def _reference(curves, qd):
 def order_beta(grid=1024):
     curves, q = W.config2(grid=grid)
     qd = _dev(q)
+    fx = oracle_rows("oracle_drawing_1024.txt")
     ref, ref_ms = _reference(curves, qd)
     _log(f"order_beta: reference {ref_ms:.1f} ms")
     rows = []
@@ -75,11 +122,12 @@ def order_beta(grid=1024):
         for beta in (2.0, 3.0, 4.0, 6.0, 8.0, 16.0, 32.0, 64.0):
             m = G.Model(curves, presets.params(presets.FP64_2D, beta=beta, taylor_order=order, max_diag_frac=0.1, far_tol=0.0))
             w, ms = _run(m, qd)
+            omax, op99, _ = _oracle_err(m, fx)
             m.close()
             err = np.abs(w - ref)
             rows.append(dict(order=order, beta=beta, max_abs_dw=float(err.max()),
-                             p99_abs_dw=float(np.quantile(err, 0.99)), ms=round(ms, 3),
-                             queries_per_s=q.shape[0] / (ms * 1e-3)))
+                             p99_abs_dw=float(np.quantile(err, 0.99)), oracle_max_abs_dw=omax, oracle_p99_abs_dw=op99,
+                             ms=round(ms, 3), queries_per_s=q.shape[0] / (ms * 1e-3)))
         _log(f"order_beta: order {order} done")
     return dict(study="order_beta", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid",
                 reference_ms=round(ref_ms, 1), rows=rows)
@@ -96,9 +144,10 @@ def subdivision(grid=1024):
         build_s = time.perf_counter() - t
         leaves = int(m.inspect(G.GWN_I_SUMMARY)[0][2])
         w, ms = _run(m, qd)
+        omax, _, _ = _oracle_err(m, oracle_rows("oracle_drawing_1024.txt"))
         m.close()
         rows.append(dict(max_diag_frac=None if frac >= 1e9 else frac, leaves=leaves, build_s=round(build_s, 3),
-                         ms=round(ms, 3), max_abs_dw=float(np.abs(w - ref).max())))
+                         ms=round(ms, 3), max_abs_dw=float(np.abs(w - ref).max()), oracle_max_abs_dw=omax))
         _log(f"subdivision: {frac} -> {leaves} leaves, {ms:.2f} ms")
     return dict(study="subdivision", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid, FP64 form "
                 f"(order {presets.FP64_2D['taylor_order']}, far_tol {presets.FP64_2D['far_tol']})", rows=rows)
@@ -113,10 +162,11 @@ def far_tol(grid=1024):
         m = G.Model(curves, presets.params(presets.FP64_2D, far_tol=tol))
         w, ms = _run(m, qd)
         nodes = m.counters(qd)["nodes"]
+        omax, _, _ = _oracle_err(m, oracle_rows("oracle_drawing_1024.txt"))
         m.close()
         err = np.abs(w - ref)
         rows.append(dict(far_tol=tol, max_abs_dw=float(err.max()), p99_abs_dw=float(np.quantile(err, 0.99)),
-                         ms=round(ms, 3), node_visits=int(nodes)))
+                         oracle_max_abs_dw=omax, ms=round(ms, 3), node_visits=int(nodes)))
         _log(f"far_tol: {tol} -> {ms:.2f} ms")
     return dict(study="far_tol", workload=f"SVG-like drawing, 19000 curves, {grid}^2 grid, order "
                 f"{presets.FP64_2D['taylor_order']} (far_tol 0: uniform beta {presets.FP64_2D['beta']})", rows=rows)
@@ -161,8 +211,60 @@ def overlap(grid=512):
                 rows=rows)
 
 
+def _model3d_rows(P, q, fx, pre, **kw):
+    """Time of one full launch and the errors on the oracle rows of a 3D
+    model (flagged rows, NaN, are counted and left out of the errors)."""
+    t = time.perf_counter()
+    m = G.Model(P, presets.params(pre, **kw))
+    build_s = time.perf_counter() - t
+    qd = _dev(q)
+    _, ms = _run(m, qd, reps=1)
+    omax, op99, nan = _oracle_err(m, fx)
+    leaves = int(m.inspect(G.GWN_I_SUMMARY)[0][2])
+    m.close()
+    return dict(leaves=leaves, build_s=round(build_s, 2), ms=round(ms, 1), queries_per_s=q.shape[0] / (ms * 1e-3),
+                oracle_max_abs_dw=omax, oracle_p99_abs_dw=op99, oracle_rows_flagged=nan)
+
+
+def order_beta_3d():
+    out = []
+    P, q = W.config3()
+    fx = oracle_rows("oracle_bodies_scene.txt")
+    rows = []
+    for order in (0, 2, 4, 6):
+        for beta in (2.0, 3.0, 5.0, 8.0, 16.0):
+            r = _model3d_rows(P, q, fx, presets.FP64_3D, taylor_order=order, beta=beta)
+            rows.append(dict(order=order, beta=beta, **r))
+            _log(f"order_beta_3d bodies: order {order} beta {beta}: {r['ms']} ms, {r['oracle_max_abs_dw']:.2e}")
+    out.append(dict(workload="bodies scene: 4096 trimmed patches, 128^3 grid; oracle rows: 512 grid + 512 "
+                             "near-surface points", rows=rows))
+    P, q = W.config4()
+    fx = oracle_rows("oracle_cad_assembly_1m.txt")
+    rows = []
+    for order in (2, 4, 6):
+        for beta in (3.0, 5.0, 8.0):
+            r = _model3d_rows(P, q, fx, presets.FP64_3D, taylor_order=order, beta=beta)
+            rows.append(dict(order=order, beta=beta, **r))
+            _log(f"order_beta_3d cad: order {order} beta {beta}: {r['ms']} ms, {r['oracle_max_abs_dw']:.2e}")
+    out.append(dict(workload="CAD assembly: 19,968 trimmed patches, 1M queries (half near-surface); oracle rows: "
+                             "512 near-surface + 512 uniform", rows=rows))
+    return dict(study="order_beta_3d", form="FP64 (leaf_far, eps_q 1e-8)", results=out)
+
+
+def subdivision_3d():
+    P, q = W.config3()
+    fx = oracle_rows("oracle_bodies_scene.txt")
+    rows = []
+    for frac in (0.1, 0.05, 0.025, 0.0125):
+        r = _model3d_rows(P, q, fx, presets.FP64_3D, max_diag_frac=frac)
+        rows.append(dict(max_diag_frac=frac, **r))
+        _log(f"subdivision_3d: {frac} -> {r['leaves']} leaves, {r['ms']} ms")
+    return dict(study="subdivision_3d", workload="bodies scene: 4096 trimmed patches, 128^3 grid, FP64 form "
+                f"(order {presets.FP64_3D['taylor_order']}, beta {presets.FP64_3D['beta']})", rows=rows)
+
+
 STUDIES = dict(order_beta=order_beta, subdivision=subdivision, far_tol=far_tol, disagreement=disagreement,
-               overlap=overlap)
+               overlap=overlap, order_beta_3d=order_beta_3d, subdivision_3d=subdivision_3d)
 
 
 def main(argv=None):

@@ -1,4 +1,4 @@
-"""Writes oracle values for seeded subsets of the two full-size 3D workloads.
+"""Writes oracle values for seeded subsets of the full-size workloads.
 
 The GPU parity tests run the engine on the whole workload (every patch, every
 query) and compare it with these values row by row.  Only oracle/ and the
@@ -11,6 +11,9 @@ seeded generators are called; nothing here touches the engine.
   bodies_scene      8 bodies, 4,096 patches (30 % with one hole); 512 seeded
                     rows of the 128^3 grid, and 512 near-surface points
                     (within 1e-2 of the surface) drawn by their own stream.
+  drawing_1024      the 2D SVG-like drawing (19,000 curves); 1,024 seeded
+                    rows of its 1024^2 grid (the parameter studies' and the
+                    headline benchmark's workload).
 
 Each file holds one row per query: the row index in the workload's query
 array (-1 for the separate near-surface points), the query coordinates and
@@ -71,11 +74,23 @@ def case_bodies():
         f"{N_PER_KIND} rows of the 128^3 grid + {N_PER_KIND} near-surface points (row -1)"
 
 
-CASES = {"cad": ("oracle_cad_assembly_1m.txt", case_cad), "bodies": ("oracle_bodies_scene.txt", case_bodies)}
+def drawing_rows(n_query=1024 * 1024):
+    return np.sort(W.Rng(202, "fixture/drawing").permutation(n_query)[:2 * N_PER_KIND])
+
+
+def case_drawing():
+    C, q = W.config2()
+    rows = drawing_rows(q.shape[0])
+    return C, rows, q[rows], f"{2 * N_PER_KIND} seeded rows of the 1024^2 grid"
+
+
+CASES = {"cad": ("oracle_cad_assembly_1m.txt", case_cad), "bodies": ("oracle_bodies_scene.txt", case_bodies),
+         "drawing": ("oracle_drawing_1024.txt", case_drawing)}
 
 
 def load(path):
-    """(rows, q, w, header dict) of a fixture file, possibly partial."""
+    """(rows, q, w, header dict) of a fixture file, possibly partial; q has
+    the workload's dimension (2 or 3 coordinates per row)."""
     hdr = {}
     data = []
     with open(path) as fh:
@@ -86,8 +101,9 @@ def load(path):
                     hdr[k.strip()] = v.strip()
                 continue
             data.append([float(x) for x in line.split()])
-    d = np.array(data).reshape(-1, 5)
-    return d[:, 0].astype(np.int64), d[:, 1:4], d[:, 4], hdr
+    dim = int(hdr.get("dim", 3))
+    d = np.array(data).reshape(-1, dim + 2)
+    return d[:, 0].astype(np.int64), d[:, 1:1 + dim], d[:, 1 + dim], hdr
 
 
 def write(name, threads):
@@ -103,6 +119,7 @@ def write(name, threads):
         unconv = int(hdr.get("oracle unconverged panels", 0))
         bound = float(hdr.get("oracle max error bound", 0.0))
     eps_on = oracle.default_eps_on(*P.bbox())
+    dim = q.shape[1]
     body = []
     if done:
         with open(path) as fh:
@@ -110,7 +127,10 @@ def write(name, threads):
     t0 = time.time()
     for s in range(done, rows.size, CHUNK):
         e = min(rows.size, s + CHUNK)
-        w = oracle.gwn3d(P, q[s:e], eps_on=eps_on, threads=threads)
+        if dim == 2:
+            w = oracle.gwn2d(P, q[s:e], eps_on=eps_on, threads=threads)
+        else:
+            w = oracle.gwn3d(P, q[s:e], eps_on=eps_on, threads=threads)
         unconv += oracle.last_unconverged
         bound = max(bound, oracle.last_errbound)
         body += [f"{int(r)} " + " ".join(f"{x:.17g}" for x in qq) + f" {v:.17g}\n"
@@ -118,11 +138,12 @@ def write(name, threads):
         with open(path + ".tmp", "w") as fh:
             fh.write(f"# oracle values on a full-size workload (written by make_fullsize_fixtures.py): {name}\n")
             fh.write(f"# subset: {what}\n")
-            fh.write(f"# patches: {P.n}\n")
+            fh.write(f"# {'curves' if dim == 2 else 'patches'}: {P.n}\n")
+            fh.write(f"# dim: {dim}\n")
             fh.write(f"# eps_on: {eps_on:.17g}\n")
             fh.write(f"# oracle unconverged panels: {unconv}\n")
             fh.write(f"# oracle max error bound: {bound:.3e}\n")
-            fh.write("# columns: row, x, y, z, w\n")
+            fh.write("# columns: row, x, y, w\n" if dim == 2 else "# columns: row, x, y, z, w\n")
             fh.writelines(body)
         os.replace(path + ".tmp", path)
         print(f"[{name}] {e}/{rows.size} rows, {time.time() - t0:.0f} s", flush=True)
@@ -130,7 +151,7 @@ def write(name, threads):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cases", nargs="*", default=["bodies", "cad"])
+    ap.add_argument("cases", nargs="*", default=["bodies", "cad", "drawing"])
     ap.add_argument("--threads", type=int, default=0)
     a = ap.parse_args()
     for name in a.cases:

@@ -354,3 +354,19 @@ def test_device_moments_match_host(which):
     finally:
         G.gwn_free(hd)
         G.gwn_free(hh)
+
+
+def test_all_direct_reference_on_the_drawing():
+    """The parameter studies' whole-grid reference (the engine with the far
+    field off: every leaf evaluated directly) against the oracle's committed
+    values on 1,024 rows of the drawing's 1024^2 grid."""
+    from paper_2605_19200_amd import studies
+    curves, q = W.config2()
+    rows, pts, ref = studies.oracle_rows("oracle_drawing_1024.txt")
+    assert np.array_equal(q[rows], pts)
+    m = G.Model(curves, presets.params(presets.FP64_2D, beta=1e8, far_tol=0.0))
+    w, ins = run(m, pts)
+    err = np.abs(w - ref)
+    print(f"all-direct reference on the drawing: max |dw| {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-10
+    m.close()
