@@ -313,7 +313,7 @@ def main():
                     help="short run for rocprofv3: one FP64 and one mixed pass over the 3D bodies scene grid")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for rocprofv3: 3 FP64 steps, then a 256 MiB device copy used to calibrate "
-                         "FETCH_SIZE/WRITE_SIZE")
+                         "FETCH_SIZE/WRITE_SIZE, then 3 steps of the mixed form (k_query2d_mixed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the engine has no multi-GPU path",
@@ -353,7 +353,13 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "queries": n, "copy_bytes": src.numel() * 8}))
+        del src, dst
+        model_m = G.Model(curves, presets.params(presets.MIXED_2D))
+        for _ in range(3):
+            G.gwn_query(model_m.h, pts, out, ins, stream)
+        torch.cuda.synchronize()
+        model_m.close()
+        print(json.dumps({"profile_run": True, "queries": n, "copy_bytes": 32 * 1024 * 1024 * 8}))
         return
 
     for _ in range(args.warmup):
