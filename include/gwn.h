@@ -158,24 +158,31 @@ typedef struct {
                               directly, as in Alg. 1.  Default 1; 2D leaves
                               are always direct (the chord angle is exact)   */
     int32_t reserved;      /* set to 0                                      */
-    double far_tol;        /* Q, 2D: error budget of the FP64 far test, in
-                              turns (units of w).  0 (default): a cluster is
+    double far_tol;        /* Q: error budget of the FP64 far test, per
+                              accepted cluster.  0 (default): a cluster is
                               far when ||q - c|| > beta * r.  > 0: each
-                              cluster gets its own factor, the smallest
-                              beta_c >= 2 for which the truncation error of
-                              its order-taylor_order expansion, bounded from
-                              its moments up to order 32 and its extent
-                              beyond, is <= far_tol wherever ||q - c|| >
+                              cluster gets its own factor beta_c, so that
+                              the truncation error of its order-taylor_order
+                              expansion is <= far_tol wherever ||q - c|| >
                               beta_c * r (the paper's future work on a
-                              geometry-aware beta, Sec. 5).  The truncation
-                              error of a query is then at most far_tol times
-                              the number of clusters accepted for it; `beta`
-                              is not used by the FP64 tests, the FP32 pass of
-                              the mixed form keeps beta_mixed.  Changing
-                              far_tol, or taylor_order while far_tol > 0,
-                              through gwn_set_params rewrites the cluster
-                              radii on the device after a device-wide
-                              synchronisation.  3D: must be 0.               */
+                              geometry-aware beta, Sec. 5).  2D (units of w,
+                              turns): the smallest beta_c >= 2 for which a
+                              bound from the moments up to order 32 and the
+                              extent beyond holds.  3D (units of w too, the
+                              solid angle over 4 pi): the smallest beta_c in
+                              [1.5, 64] for which an estimate from the two
+                              first omitted harmonic degrees, sampled over
+                              256 directions, holds (an estimate, not a
+                              bound); with leaf_far the same applies to
+                              leaves.  The truncation error of a query is
+                              then about far_tol times the number of
+                              clusters accepted for it; `beta` is not used
+                              by the FP64 tests, the FP32 pass of the mixed
+                              form keeps beta_mixed.  Changing far_tol, or
+                              taylor_order while far_tol > 0, through
+                              gwn_set_params rewrites the cluster radii on
+                              the device after a device-wide
+                              synchronisation.                              */
 } gwn_params;
 
 /* Fill *p with the defaults listed above. */
@@ -330,10 +337,11 @@ gwn_status gwn_model_bytes(gwn_handle h, int64_t *resident, int64_t *per_query_s
  *                   parameter square -- 10 doubles.  A leaf cut from a
  *                   trimmed patch holds its clipped loops (closed, in loop
  *                   order); an untrimmed leaf has none.
- *   GWN_I_FARBETA   2D only, per node: the far-field factor the FP64 test
- *                   uses under the handle's current parameters -- beta, or
- *                   with far_tol > 0 the cluster's own beta_c (+inf when no
- *                   factor meets the budget); 0 for leaves.  1 double.
+ *   GWN_I_FARBETA   per node: the far-field factor the FP64 test uses
+ *                   under the handle's current parameters -- beta, or with
+ *                   far_tol > 0 the cluster's own beta_c (+inf when no
+ *                   factor meets the budget); 0 for 2D leaves (never far
+ *                   tested).  1 double.
  */
 enum { GWN_I_SUMMARY = 0, GWN_I_LEAVES = 1, GWN_I_NODES = 2, GWN_I_MOMENTS = 3, GWN_I_UNCENTERED = 4,
        GWN_I_COMPLEX = 5, GWN_I_MULTIPOLE = 6, GWN_I_FARBETA = 7, GWN_I_LEAF_TRIMS = 8 };

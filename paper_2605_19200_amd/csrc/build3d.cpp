@@ -439,7 +439,8 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     std::vector<std::array<int, 3>> qcount(nl);
     // multipole moments of each leaf about its own centroid (far field at
     // orders above 2; see multipole3d.h)
-    std::vector<cplx> LN((size_t)nl * kMpoleTerms, cplx(0, 0));
+    // (two degrees beyond the far field's, for the error-budgeted far test)
+    std::vector<cplx> LN((size_t)nl * kMpoleTermsTail, cplx(0, 0));
     std::vector<double> LC(3 * (size_t)nl, 0.0);
     // leaves are independent: split them over host threads
     auto leaf_work = [&](int li) {
@@ -502,9 +503,9 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         double *cl = &LC[3 * li];
         for (int a = 0; a < 3; ++a)
             cl[a] = Wt[li] > 0.0 ? WC[3 * li + a] / Wt[li] : 0.5 * (LO[3 * li + a] + HI[3 * li + a]);
-        cplx *nl_out = &LN[(size_t)li * kMpoleTerms];
+        cplx *nl_out = &LN[(size_t)li * kMpoleTermsTail];
         scatter(gx.data(), gw.data(), g, gx.data(), gw.data(), g,
-                [&](const QNode3 &node, double) { mpole_add_node(node.x, node.n, cl, kMaxL3, nl_out); });
+                [&](const QNode3 &node, double) { mpole_add_node(node.x, node.n, cl, kMaxLTail3, nl_out); });
     };
     {
         const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
@@ -528,17 +529,47 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     // diagonal), which keeps the FP32 mirror in range.
     {
         const size_t nn = m.tree.nodes.size();
-        std::vector<cplx> NN(nn * kMpoleTerms, cplx(0, 0));
+        std::vector<cplx> NN(nn * kMpoleTermsTail, cplx(0, 0));
         for (size_t ii = nn; ii-- > 0;) {
             const HostNode &h = m.tree.nodes[ii];
-            cplx *dst = &NN[ii * kMpoleTerms];
+            cplx *dst = &NN[ii * kMpoleTermsTail];
             if (h.is_leaf) {
-                mpole_translate(&LN[(size_t)h.leaf * kMpoleTerms], &LC[3 * (size_t)h.leaf], h.c, kMaxL3, dst);
+                mpole_translate(&LN[(size_t)h.leaf * kMpoleTermsTail], &LC[3 * (size_t)h.leaf], h.c, kMaxLTail3,
+                                dst);
             } else {
                 const HostNode &a = m.tree.nodes[ii + 1], &b = m.tree.nodes[h.right];
-                mpole_translate(&NN[(ii + 1) * kMpoleTerms], a.c, h.c, kMaxL3, dst);
-                mpole_translate(&NN[(size_t)h.right * kMpoleTerms], b.c, h.c, kMaxL3, dst);
+                mpole_translate(&NN[(ii + 1) * kMpoleTermsTail], a.c, h.c, kMaxLTail3, dst);
+                mpole_translate(&NN[(size_t)h.right * kMpoleTermsTail], b.c, h.c, kMaxLTail3, dst);
             }
+        }
+        // per node, the largest magnitude of each degree's term at unit
+        // distance over kTailDirs directions (a Fibonacci lattice of the
+        // sphere), for far_beta3d
+        m.tail3.assign(nn * kMaxLTail3, 0.0);
+        {
+            constexpr int kTailDirs = 256;
+            double dirs[kTailDirs][3];
+            for (int k = 0; k < kTailDirs; ++k) {
+                const double z = 1.0 - (2.0 * k + 1.0) / kTailDirs, s = std::sqrt(std::max(0.0, 1.0 - z * z));
+                const double ph = 2.399963229728653 * k;   // golden angle
+                dirs[k][0] = s * std::cos(ph);
+                dirs[k][1] = s * std::sin(ph);
+                dirs[k][2] = z;
+            }
+            const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nthreads; ++t)
+                pool.emplace_back([&, t] {
+                    double T[kMaxLTail3];
+                    for (size_t ii = t; ii < nn; ii += nthreads) {
+                        double *A = &m.tail3[ii * kMaxLTail3];
+                        for (int k = 0; k < kTailDirs; ++k) {
+                            mpole_degree_terms(dirs[k], &NN[ii * kMpoleTermsTail], kMaxLTail3, T);
+                            for (int l = 0; l < kMaxLTail3; ++l) A[l] = std::max(A[l], std::fabs(T[l]));
+                        }
+                    }
+                });
+            for (auto &th : pool) th.join();
         }
         m.mpole.assign(nn * kMpoleStride, 0.0);
         for (size_t ii = 0; ii < nn; ++ii) {
@@ -549,7 +580,7 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
             for (int l = 1; l <= kMaxL3; ++l) {
                 const double sc = std::pow(ir, l + 1);
                 for (int mm = 0; mm <= l; ++mm) {
-                    const cplx v = NN[ii * kMpoleTerms + mp_index(l, mm)] * sc;
+                    const cplx v = NN[ii * kMpoleTermsTail + mp_index(l, mm)] * sc;
                     o[2 + 2 * mp_index(l, mm)] = v.real();
                     o[3 + 2 * mp_index(l, mm)] = v.imag();
                 }
@@ -584,6 +615,32 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     return GWN_OK;
 }
 
+// The order-p expansion keeps the degrees l <= p + 1; its error at distance
+// rho is estimated by the first two omitted degrees, the second carrying a
+// geometric bound on the rest (the degree-l term decays as rho^-(l+1), and
+// successive degrees shrink at least as r / rho):
+//   E(rho) = 2 [A_{p+2} rho^-(p+3) + A_{p+3} rho^-(p+4) / (1 - r / rho)],
+// the factor 2 for the sampled directions' maximum.  E falls with rho, so
+// the factor is found by bisection.
+double far_beta3d(const double *A, double r, int order, double tol)
+{
+    const int l1 = order + 2, l2 = order + 3;
+    if (l2 > kMaxLTail3 || !(tol > 0.0) || !(r > 0.0)) return HUGE_VAL;
+    const double budget = 4.0 * kPi * tol;
+    auto err = [&](double beta) {
+        const double rho = beta * r;
+        return 2.0 * (A[l1 - 1] * std::pow(rho, -(l1 + 1)) + A[l2 - 1] * std::pow(rho, -(l2 + 1)) / (1.0 - 1.0 / beta));
+    };
+    if (err(kBetaMin3) <= budget) return kBetaMin3;
+    double lo = kBetaMin3, hi = 64.0;
+    if (err(hi) > budget) return HUGE_VAL;
+    for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (err(mid) <= budget) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
 void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims)
 {
     const auto &T = m.tree.nodes;
@@ -594,6 +651,14 @@ void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims
         std::memset(&n, 0, sizeof n);
         for (int a = 0; a < 3; ++a) n.c[a] = h.c[a];
         n.r2 = h.r * h.r;
+        // the FP32 pass of the mixed form keeps r^2 (its factor is
+        // beta_mixed); the FP64 test of an error-budgeted model compares
+        // with (beta_c r)^2 at beta = 1
+        double far_r2 = n.r2;
+        if (m.params.far_tol > 0.0 && h.r > 0.0) {
+            const double bc = far_beta3d(&m.tail3[i * kMaxLTail3], h.r, m.params.taylor_order, m.params.far_tol);
+            far_r2 = std::isfinite(bc) ? (bc * h.r) * (bc * h.r) : HUGE_VAL;
+        }
         if (h.is_leaf) {
             for (int a = 0; a < 3; ++a) { n.t[a] = h.lo[a]; n.t[3 + a] = h.hi[a]; }
             n.right = -1 - h.leaf;
@@ -635,6 +700,7 @@ void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims
         }
         for (int a = 0; a < 3; ++a) n.fc[a] = (float)n.c[a];
         n.fr2 = (float)n.r2;
+        n.r2 = far_r2;
         for (int k = 0; k < 22; ++k) n.ft[k] = (float)n.t[k];
     }
     prims.assign(m.leaf_src.size(), Prim3{});

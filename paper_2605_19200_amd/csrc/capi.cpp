@@ -65,7 +65,6 @@ static gwn_status check_query_params(int dim, const gwn_params *p)
     if (!(p->eps_q > 0)) return fail(GWN_EINVAL, "eps_q must be > 0");
     if (p->leaf_far != 0 && p->leaf_far != 1) return fail(GWN_EINVAL, "leaf_far must be 0 or 1");
     if (!(p->far_tol >= 0) || !std::isfinite(p->far_tol)) return fail(GWN_EINVAL, "far_tol must be finite and >= 0");
-    if (dim == 3 && p->far_tol != 0.0) return fail(GWN_EINVAL, "far_tol applies to 2D models only");
     return GWN_OK;
 }
 
@@ -87,8 +86,8 @@ void refresh_dev_params(Model &m)
     m.dev.dim = m.dim;
     m.dev.order = p.taylor_order;
     m.dev.precision = p.precision;
-    // error-budgeted 2D far test: the cluster radii carry their own factor
-    m.dev.beta2 = (m.dim == 2 && p.far_tol > 0.0) ? 1.0 : p.beta * p.beta;
+    // error-budgeted far test: the cluster radii carry their own factor
+    m.dev.beta2 = p.far_tol > 0.0 ? 1.0 : p.beta * p.beta;
     m.dev.beta2_mixed = p.beta_mixed * p.beta_mixed;
     m.dev.band = p.reclass_band;
     for (int a = 0; a < 3; ++a) {
@@ -398,16 +397,25 @@ extern "C" gwn_status gwn_set_params(gwn_handle h, const gwn_params *params)
     if (s) return s;
     const gwn_params old = h->m.params;
     h->m.params = p;
-    const bool radii = h->m.dim == 2 && (p.far_tol != old.far_tol ||
-                                        (p.far_tol > 0.0 && p.taylor_order != old.taylor_order));
+    const bool radii = p.far_tol != old.far_tol || (p.far_tol > 0.0 && p.taylor_order != old.taylor_order);
     if (radii && h->m.d_arena) {
         // the far radii live in the node records: rewrite them once no
         // launch can still read them
         std::vector<Node2> n2; std::vector<Hot2> h2; std::vector<Prim2> p2;
-        pack2d(h->m, n2, h2, p2);
+        std::vector<Node3> n3; std::vector<Prim3> p3;
+        const void *src;
+        void *dst;
+        size_t bytes;
+        if (h->m.dim == 2) {
+            pack2d(h->m, n2, h2, p2);
+            src = h2.data(); dst = (void *)h->m.dev.hot; bytes = h2.size() * sizeof(Hot2);
+        } else {
+            pack3d(h->m, n3, p3);
+            src = n3.data(); dst = (void *)h->m.dev.nodes; bytes = n3.size() * sizeof(Node3);
+        }
         hipError_t e = hipSetDevice(h->m.device);
         if (e == hipSuccess) e = hipDeviceSynchronize();
-        if (e == hipSuccess) e = hipMemcpy((void *)h->m.dev.hot, h2.data(), h2.size() * sizeof(Hot2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             h->m.params = old;
             return fail(GWN_EHIP, std::string("far radii update: ") + hipGetErrorString(e));
@@ -622,16 +630,16 @@ extern "C" gwn_status gwn_inspect(gwn_handle h, int32_t what, double *out, int64
         break;
     }
     case GWN_I_FARBETA: {
-        if (d != 2) return fail(GWN_EINVAL, "far-field factors are inspected for 2D models only");
         width = 1;
         items = (int64_t)m.tree.nodes.size();
         buf.assign(items, 0.0);
         for (int64_t i = 0; i < items; ++i) {
             const HostNode &n = m.tree.nodes[i];
-            if (n.is_leaf) continue;
-            buf[i] = m.params.far_tol > 0.0 && n.r > 0.0
-                         ? far_beta2d(&m.tail2[i * kTailStride2D], m.params.taylor_order, m.params.far_tol)
-                         : m.params.beta;
+            // 2D leaves are never far-tested; 3D leaves are with leaf_far
+            if (n.is_leaf && d == 2) continue;
+            if (!(m.params.far_tol > 0.0 && n.r > 0.0)) buf[i] = m.params.beta;
+            else if (d == 2) buf[i] = far_beta2d(&m.tail2[i * kTailStride2D], m.params.taylor_order, m.params.far_tol);
+            else buf[i] = far_beta3d(&m.tail3[i * kMaxLTail3], n.r, m.params.taylor_order, m.params.far_tol);
         }
         break;
     }

@@ -45,6 +45,10 @@ constexpr int kMaxOrder3D = 6;   // harmonic degree <= 7, see multipole3d.h
 constexpr int kMaxL3 = kMaxOrder3D + 1;   // highest solid-harmonic degree
 constexpr int kMpoleTerms = 35;           // (l, m) with 1 <= l <= 7, 0 <= m <= l
 constexpr int kMpoleStride = 72;          // per node: 1/r, 0, then 35 (re, im) pairs
+// The host also carries two more degrees, for the error-budgeted far test
+// (far_beta3d): per node, the largest magnitude of each degree's term.
+constexpr int kMaxLTail3 = kMaxL3 + 2;
+constexpr int kMpoleTermsTail = kMaxLTail3 * (kMaxLTail3 + 3) / 2;   // (l, m) with 1 <= l <= 9
 struct alignas(128) Node2 {
     double c[2];
     double r2;
@@ -230,6 +234,7 @@ struct Model {
     std::vector<int64_t> leaf_q_begin, leaf_q_count;
     std::vector<std::array<int, 3>> leaf_q_rules;
     std::vector<double> mpole;        // 3D: per node kMpoleStride doubles (multipole3d.h)
+    std::vector<double> tail3;        // 3D: per node kMaxLTail3 doubles (far_beta3d)
     // device
     int device = -1;
     void *d_arena = nullptr;
@@ -247,6 +252,14 @@ struct Model {
 // is at most `tol` (in turns) wherever ||q - c|| > beta r.  +inf when no
 // beta meets the budget.
 double far_beta2d(const double *tail, int order, double tol);
+// Far-field factor of one 3D cluster under an error budget (build3d.cpp):
+// the smallest beta in [kBetaMin3, 64] for which the estimated truncation
+// error of its order-`order` expansion is at most 4 pi tol (solid angle)
+// wherever ||q - c|| > beta r; +inf when none is.  A[l - 1], l = 1 ..
+// kMaxLTail3: the largest magnitude of the cluster's degree-l term at unit
+// distance.
+constexpr double kBetaMin3 = 1.5;
+double far_beta3d(const double *A, double r, int order, double tol);
 // Chord moments of every 2D cluster on `device` (moments2d.hip): cmom2 and
 // tail2 as the host build lays them out, except tail2's rho entries, which
 // the caller fills.  chord_ends holds (ax, ay, bx, by) per leaf in DFS order;

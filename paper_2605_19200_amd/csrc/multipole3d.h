@@ -31,8 +31,8 @@ using cplx = std::complex<double>;
 
 // R_l^m(d) and grad R_l^m(d) for 0 <= m <= l <= L (forward differentiation of
 // the recurrences).
-inline void regular_harmonics(const double d[3], int L, cplx R[kMaxL3 + 1][kMaxL3 + 1],
-                              cplx dR[kMaxL3 + 1][kMaxL3 + 1][3])
+inline void regular_harmonics(const double d[3], int L, cplx R[kMaxLTail3 + 1][kMaxLTail3 + 1],
+                              cplx dR[kMaxLTail3 + 1][kMaxLTail3 + 1][3])
 {
     const double x = d[0], y = d[1], z = d[2];
     const double rho2 = x * x + y * y + z * z;
@@ -65,10 +65,10 @@ inline void regular_harmonics(const double d[3], int L, cplx R[kMaxL3 + 1][kMaxL
 }
 
 // Adds the contribution of one quadrature node (position x, weighted normal
-// nw) to the moments N (kMpoleTerms entries) about centre c.
+// nw) to the moments N (entries for 1 <= l <= L) about centre c.
 inline void mpole_add_node(const double x[3], const double nw[3], const double c[3], int L, cplx *N)
 {
-    cplx R[kMaxL3 + 1][kMaxL3 + 1], dR[kMaxL3 + 1][kMaxL3 + 1][3];
+    cplx R[kMaxLTail3 + 1][kMaxLTail3 + 1], dR[kMaxLTail3 + 1][kMaxLTail3 + 1][3];
     const double d[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
     regular_harmonics(d, L, R, dR);
     for (int l = 1; l <= L; ++l)
@@ -82,7 +82,7 @@ inline void mpole_add_node(const double x[3], const double nw[3], const double c
 // Adds to Ndst the moments Nsrc (about c_src) translated to c_dst.
 inline void mpole_translate(const cplx *Nsrc, const double c_src[3], const double c_dst[3], int L, cplx *Ndst)
 {
-    cplx R[kMaxL3 + 1][kMaxL3 + 1], dR[kMaxL3 + 1][kMaxL3 + 1][3];
+    cplx R[kMaxLTail3 + 1][kMaxLTail3 + 1], dR[kMaxLTail3 + 1][kMaxLTail3 + 1][3];
     const double d[3] = {c_src[0] - c_dst[0], c_src[1] - c_dst[1], c_src[2] - c_dst[2]};
     regular_harmonics(d, L, R, dR);
     auto getR = [&](int n, int mu) -> cplx {
@@ -104,6 +104,35 @@ inline void mpole_translate(const cplx *Nsrc, const double c_src[3], const doubl
                 }
             Ndst[mp_index(l, m)] += s;
         }
+}
+
+// The cluster's solid-angle terms of each degree at offset d = q - c from
+// its centre: T[l - 1] = I_l^0 N_l^0 + 2 sum_{m >= 1} Re(I_l^m N_l^m) for
+// l = 1 .. L, with the irregular harmonics I_l^m(d) of the device's
+// recurrences (unscaled moments N).
+inline void mpole_degree_terms(const double d[3], const cplx *N, int L, double *T)
+{
+    const double inv2 = 1.0 / (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int l = 1; l <= L; ++l) T[l - 1] = 0.0;
+    cplx mm(std::sqrt(inv2), 0.0);
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) mm = mm * cplx(d[0], d[1]) * ((2.0 * m - 1.0) * inv2);
+        const double wgt = m == 0 ? 1.0 : 2.0;
+        cplx prev(0, 0), cur = mm;
+        for (int l = m; l <= L; ++l) {
+            if (l > m) {
+                const double a = (2.0 * l - 1.0) * d[2] * inv2;
+                const double b = (double)((l + m - 1) * (l - m - 1)) * inv2;
+                const cplx nx = a * cur - b * prev;
+                prev = cur;
+                cur = nx;
+            }
+            if (l >= 1) {
+                const cplx v = N[mp_index(l, m)];
+                T[l - 1] += wgt * (cur.real() * v.real() - cur.imag() * v.imag());
+            }
+        }
+    }
 }
 
 }  // namespace gwn

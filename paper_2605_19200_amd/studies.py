@@ -251,6 +251,37 @@ def order_beta_3d():
     return dict(study="order_beta_3d", form="FP64 (leaf_far, eps_q 1e-8)", results=out)
 
 
+def far_tol_3d():
+    """Error-budgeted 3D far test: one model per workload, the budget changed
+    through set_params (which rewrites the cluster radii), against the
+    uniform factor of the FP64 preset."""
+    out = []
+    for name, fixture, make, settings in (
+            ("bodies scene: 4096 trimmed patches, 128^3 grid", "oracle_bodies_scene.txt", W.config3,
+             [(6, 0.0), (6, 1e-7), (6, 3e-8), (6, 1e-8), (6, 3e-9), (6, 1e-9), (4, 1e-8), (4, 1e-9)]),
+            ("CAD assembly: 19,968 trimmed patches, 1M queries", "oracle_cad_assembly_1m.txt", W.config4,
+             [(6, 0.0), (6, 1e-7), (6, 1e-8), (6, 1e-9)])):
+        P, q = make()
+        fx = oracle_rows(fixture)
+        m = G.Model(P, presets.params(presets.FP64_3D))
+        qd = _dev(q)
+        rows = []
+        for order, tol in settings:
+            m.set(taylor_order=order, far_tol=tol)
+            fb = m.inspect(G.GWN_I_FARBETA)[:, 0]
+            _, ms = _run(m, qd, reps=1)
+            omax, op99, nan = _oracle_err(m, fx)
+            rows.append(dict(order=order, far_tol=tol, beta_c_median=float(np.median(fb)),
+                             beta_c_max=float(np.max(fb)), ms=round(ms, 1), queries_per_s=q.shape[0] / (ms * 1e-3),
+                             oracle_max_abs_dw=omax, oracle_p99_abs_dw=op99, oracle_rows_flagged=nan))
+            _log(f"far_tol_3d {name.split(':')[0]}: order {order} far_tol {tol:g}: {ms:.1f} ms, {omax:.2e} "
+                 f"(beta_c median {np.median(fb):.2f})")
+        m.close()
+        out.append(dict(workload=name, rows=rows))
+    return dict(study="far_tol_3d", form=f"FP64 (leaf_far, eps_q 1e-8, uniform beta {presets.FP64_3D['beta']} "
+                "when far_tol = 0)", results=out)
+
+
 def subdivision_3d():
     P, q = W.config3()
     fx = oracle_rows("oracle_bodies_scene.txt")
@@ -264,7 +295,8 @@ def subdivision_3d():
 
 
 STUDIES = dict(order_beta=order_beta, subdivision=subdivision, far_tol=far_tol, disagreement=disagreement,
-               overlap=overlap, order_beta_3d=order_beta_3d, subdivision_3d=subdivision_3d)
+               overlap=overlap, order_beta_3d=order_beta_3d, subdivision_3d=subdivision_3d,
+               far_tol_3d=far_tol_3d)
 
 
 def main(argv=None):

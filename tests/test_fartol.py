@@ -1,9 +1,10 @@
-"""Error-budgeted 2D far test (far_tol > 0): each cluster's own factor beta_c
-must keep the truncation error of its order-p chord expansion within the
-budget at every point with ||q - c|| > beta_c r.  Checked on the CPU from a
-host-only build: the exact angle of the cluster's chords (atan2 per chord,
-the plain definition) against the truncated Laurent series of the chord
-integral, evaluated just outside beta_c r in many directions."""
+"""Error-budgeted far test (far_tol > 0): each cluster's own factor beta_c
+must keep the truncation error of its order-p expansion within the budget at
+every point with ||q - c|| > beta_c r.  Checked on the CPU from host-only
+builds.  2D: the exact angle of the cluster's chords (atan2 per chord, the
+plain definition) against the truncated Laurent series of the chord integral,
+evaluated just outside beta_c r in many directions.  3D: the oracle's direct
+solid angle of the cluster's patches against its order-p multipole series."""
 import numpy as np
 import pytest
 
@@ -113,10 +114,67 @@ def test_uniform_beta_without_budget_and_set_params():
     G.gwn_free(h)
 
 
-def test_rejected_in_3d():
-    P = W.config3(grid=4)[0]
-    with pytest.raises(G.GwnError):
-        G.gwn_build3d(P, G.gwn_default_params(device=-1, far_tol=1e-8, max_diag_frac=10.0))
+def _host3d(P, **kw):
+    return G.gwn_build3d(P, G.gwn_default_params(device=-1, max_diag_frac=10.0, **kw))
+
+
+@pytest.mark.parametrize("order,tol", [(2, 1e-6), (4, 1e-8), (6, 1e-9)])
+def test_3d_estimate_holds_outside_beta_c(oracle, order, tol):
+    """3D: beta_c comes from an estimate of the first two omitted harmonic
+    degrees (with a factor 2), so the error of the order-p multipole series
+    against the oracle's direct solid angle of the cluster's patches, just
+    outside beta_c r and further out, stays within the budget."""
+    from tests.test_hostbuild3d import multipole_omega
+    P = W.config3(grid=0)[0].subset(range(0, 4096, 13))
+    h = _host3d(P, taylor_order=order, far_tol=tol)
+    nodes = G.gwn_inspect(h, G.GWN_I_NODES)
+    MP = G.gwn_inspect(h, G.GWN_I_MULTIPOLE)
+    leaves = G.gwn_inspect(h, G.GWN_I_LEAVES)
+    fb = G.gwn_inspect(h, G.GWN_I_FARBETA)[:, 0]
+    G.gwn_free(h)
+    assert np.all(fb >= 1.5) and np.all(np.isfinite(fb))
+    end = _subtree_ends(nodes)
+    rng = W.Rng(17, "fartol3d")
+    worst, checked = 0.0, 0
+    for i in range(0, nodes.shape[0], 9):
+        bc, r = fb[i], nodes[i, 6]
+        if r <= 0:
+            continue
+        src = sorted({int(leaves[int(nodes[j, 1]), 0]) for j in range(i, end[i]) if nodes[j, 0]})
+        c = nodes[i, 3:6]
+        d = rng.uniform(48, -1.0, 1.0).reshape(16, 3)
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        qs = np.concatenate([c + bc * r * (1 + 1e-9) * d, c + 1.5 * bc * r * d])
+        direct = oracle.gwn3d(P.subset(src), qs)
+        approx = np.array([multipole_omega(MP[i], q - c, order) for q in qs]) / (4 * np.pi)
+        worst = max(worst, np.abs(direct - approx).max() / tol)
+        checked += qs.shape[0]
+    assert checked > 2000
+    assert worst <= 1.0, worst
+
+
+def test_3d_factor_follows_budget_and_order():
+    P = W.config3(grid=0)[0].subset(range(0, 4096, 13))
+    fbs = {}
+    for order, tol in [(4, 1e-6), (4, 1e-9), (6, 1e-9)]:
+        h = _host3d(P, taylor_order=order, far_tol=tol)
+        fbs[(order, tol)] = G.gwn_inspect(h, G.GWN_I_FARBETA)[:, 0]
+        G.gwn_free(h)
+    assert np.all(fbs[(4, 1e-9)] >= fbs[(4, 1e-6)])
+    assert np.any(fbs[(4, 1e-9)] > fbs[(4, 1e-6)])
+    # one more order tightens most factors (an estimate, not a bound, so not all)
+    assert np.mean(fbs[(6, 1e-9)] <= fbs[(4, 1e-9)]) > 0.9
+    h = _host3d(P, taylor_order=6, beta=4.0)
+    assert np.all(G.gwn_inspect(h, G.GWN_I_FARBETA)[:, 0] == 4.0)
+    p = G.gwn_get_params(h)
+    p.far_tol = 1e-9
+    G.gwn_set_params(h, p)
+    assert np.array_equal(G.gwn_inspect(h, G.GWN_I_FARBETA)[:, 0], fbs[(6, 1e-9)])
+    # a loose budget floors at 1.5
+    p.far_tol = 1.0
+    G.gwn_set_params(h, p)
+    assert np.all(G.gwn_inspect(h, G.GWN_I_FARBETA)[:, 0] == 1.5)
+    G.gwn_free(h)
 
 
 def test_loose_budget_floors_at_two_and_tight_budget_is_finite():
