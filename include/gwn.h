@@ -109,6 +109,42 @@ typedef struct {
     const double *trim_cp_w;       /* [n_trim_cp]      */
 } gwn_patches3d;
 
+/* 3D NURBS input, converted to gwn_patches3d by gwn_nurbs3d_extract (Sec. 3.1:
+ * trimmed NURBS surfaces, Bezier extraction as in Sec. 3.2).  Surface i has
+ * degrees degree_u[i], degree_v[i] (1..3 each) and an n_u[i] x n_v[i] net:
+ * control point (a, b) (a indexes u) is cp_xyz[3*k..3*k+2] with weight
+ * cp_w[k] (finite, > 0), k = cp_offset[i] + n_v[i]*a + b; cp_offset[i+1] -
+ * cp_offset[i] must equal n_u[i] * n_v[i].  Its knot vectors are
+ * knots_u[knot_u_offset[i] ..] (n_u[i] + degree_u[i] + 1 values) and
+ * knots_v[knot_v_offset[i] ..], each clamped, non-decreasing, finite, no
+ * interior value repeated more than degree + 1 times (as for
+ * gwn_nurbs2d); the parameter domain is [U_p, U_n] x [V_q, V_n].  Its trim
+ * curves are trim_offset[i] .. trim_offset[i+1]-1 (none: the whole domain is
+ * visible): 2D NURBS curves in (u, v) of degree 1 or 2, laid out as in
+ * gwn_nurbs2d (trim_cp_offset / trim_cp_uv / trim_cp_w, trim_knot_offset /
+ * trim_knots), lying in the domain and forming closed loops there with the
+ * orientation rules of gwn_patches3d (outer boundary counter-clockwise and
+ * given explicitly, holes clockwise). */
+typedef struct {
+    int64_t n_surfaces;
+    const int32_t *degree_u, *degree_v;   /* [n_surfaces] */
+    const int32_t *n_u, *n_v;             /* [n_surfaces] */
+    const int64_t *cp_offset;             /* [n_surfaces + 1], cp_offset[0] == 0 */
+    const double *cp_xyz;                 /* [3 * n_cp] */
+    const double *cp_w;                   /* [n_cp] */
+    const int64_t *knot_u_offset;         /* [n_surfaces + 1], [0] == 0 */
+    const double *knots_u;
+    const int64_t *knot_v_offset;         /* [n_surfaces + 1], [0] == 0 */
+    const double *knots_v;
+    const int64_t *trim_offset;           /* [n_surfaces + 1], [0] == 0 */
+    const int32_t *trim_degree;           /* [n_trim] */
+    const int64_t *trim_cp_offset;        /* [n_trim + 1], [0] == 0 */
+    const double *trim_cp_uv;             /* [2 * n_trim_cp] */
+    const double *trim_cp_w;              /* [n_trim_cp] */
+    const int64_t *trim_knot_offset;      /* [n_trim + 1], [0] == 0 */
+    const double *trim_knots;
+} gwn_nurbs3d;
+
 /* Parameters.  Build-time fields fix the tree; query-time fields (marked Q)
  * may be changed later with gwn_set_params. */
 typedef struct {
@@ -213,6 +249,28 @@ gwn_status gwn_build2d(const gwn_curves2d *curves, const gwn_params *params, gwn
  * too small). */
 gwn_status gwn_nurbs2d_extract(const gwn_nurbs2d *in, int64_t *n_segments, int64_t *n_points,
                                int32_t *degree, int64_t *cp_offset, double *cp_xy, double *cp_w);
+
+/* Bezier extraction of trimmed NURBS surfaces into the gwn_patches3d layout.
+ * Every knot span (u, v) of positive size becomes one rational bicubic
+ * patch (the span's Bezier net by blossoming, raised to degree 3 in each
+ * direction by exact degree elevation), spans in surface order, u-major.
+ * A trimmed surface's loops are clipped to each span and mapped to the
+ * span's unit square, as degree-2 trim curves; a span that holds none of
+ * the visible region is dropped, and a span that is wholly visible gets no
+ * trim curves.  Two calls, as gwn_nurbs2d_extract: with cp_xyz == NULL only
+ * *n_patches, *n_trims and *n_trim_cp are written; then, with those holding
+ * the capacities of cp_xyz[48 * n], cp_w[16 * n], trim_offset[n + 1],
+ * trim_degree[n_trims], trim_cp_offset[n_trims + 1], trim_cp_uv[2 * n_trim_cp]
+ * and trim_cp_w[n_trim_cp], the arrays are filled and the counts receive the
+ * sizes written.  Host memory owned by the caller.  Errors: GWN_EINVAL (NULL
+ * pointers, bad degrees, counts, offsets or knot vectors, non-finite data,
+ * weights <= 0, trim curves outside the domain or not closed, a trim loop
+ * that passes through a junction of two trim curves on an interior knot
+ * line or touches one tangentially -- the message names the surface and
+ * the knot --, capacity too small). */
+gwn_status gwn_nurbs3d_extract(const gwn_nurbs3d *in, int64_t *n_patches, int64_t *n_trims, int64_t *n_trim_cp,
+                               double *cp_xyz, double *cp_w, int64_t *trim_offset, int32_t *trim_degree,
+                               int64_t *trim_cp_offset, double *trim_cp_uv, double *trim_cp_w);
 
 /* Build a 3D model (Alg. 1 preprocessing, moments by Gauss-Legendre quadrature
  * over the trimmed domain via Green's theorem, Sec. 3.1).  Errors as for

@@ -372,6 +372,49 @@ extern "C" gwn_status gwn_nurbs2d_extract(const gwn_nurbs2d *in, int64_t *n_segm
     return GWN_OK;
 }
 
+extern "C" gwn_status gwn_nurbs3d_extract(const gwn_nurbs3d *in, int64_t *n_patches, int64_t *n_trims,
+                                          int64_t *n_trim_cp, double *cp_xyz, double *cp_w, int64_t *trim_offset,
+                                          int32_t *trim_degree, int64_t *trim_cp_offset, double *trim_cp_uv,
+                                          double *trim_cp_w)
+{
+    if (!in || !n_patches || !n_trims || !n_trim_cp) return fail(GWN_EINVAL, "NULL input or count pointer");
+    NurbsPatches x;
+    std::string err;
+    try {
+        if (!extract_nurbs3d(*in, x, err)) return fail(GWN_EINVAL, err);
+    } catch (const std::bad_alloc &) {
+        return fail(GWN_ENOMEM, "host allocation failed during NURBS extraction");
+    }
+    const int64_t np = (int64_t)x.cp_w.size() / 16, nt = (int64_t)x.trim_degree.size(),
+                  nc = (int64_t)x.trim_cp_w.size();
+    if (!cp_xyz) {
+        *n_patches = np;
+        *n_trims = nt;
+        *n_trim_cp = nc;
+        return GWN_OK;
+    }
+    if (!cp_w || !trim_offset || (nt > 0 && (!trim_degree || !trim_cp_offset || !trim_cp_uv || !trim_cp_w)))
+        return fail(GWN_EINVAL, "NULL output array");
+    if (*n_patches < np || *n_trims < nt || *n_trim_cp < nc)
+        return fail(GWN_EINVAL, "output capacity too small: need " + std::to_string(np) + " patches, " +
+                                    std::to_string(nt) + " trim curves and " + std::to_string(nc) + " trim points");
+    std::copy(x.cp_xyz.begin(), x.cp_xyz.end(), cp_xyz);
+    std::copy(x.cp_w.begin(), x.cp_w.end(), cp_w);
+    std::copy(x.trim_offset.begin(), x.trim_offset.end(), trim_offset);
+    if (nt > 0) {
+        std::copy(x.trim_degree.begin(), x.trim_degree.end(), trim_degree);
+        std::copy(x.trim_cp_offset.begin(), x.trim_cp_offset.end(), trim_cp_offset);
+        std::copy(x.trim_cp_uv.begin(), x.trim_cp_uv.end(), trim_cp_uv);
+        std::copy(x.trim_cp_w.begin(), x.trim_cp_w.end(), trim_cp_w);
+    } else if (trim_cp_offset) {
+        trim_cp_offset[0] = 0;
+    }
+    *n_patches = np;
+    *n_trims = nt;
+    *n_trim_cp = nc;
+    return GWN_OK;
+}
+
 extern "C" gwn_status gwn_build3d(const gwn_patches3d *patches, const gwn_params *params, gwn_handle *out)
 {
     if (!patches) return fail(GWN_EINVAL, "patches is NULL");

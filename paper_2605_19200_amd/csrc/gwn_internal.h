@@ -273,6 +273,16 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
 // invalid input
 bool extract_nurbs2d(const gwn_nurbs2d &in, std::vector<int32_t> &deg, std::vector<int64_t> &off,
                      std::vector<double> &xy, std::vector<double> &w, std::string &err);
+// Bezier extraction of trimmed NURBS surfaces (nurbs.cpp), in the layout of
+// gwn_patches3d plus each patch's source surface; false with err set on
+// invalid input
+struct NurbsPatches {
+    std::vector<double> cp_xyz, cp_w;
+    std::vector<int64_t> trim_offset, trim_cp_offset, source;
+    std::vector<int32_t> trim_degree;
+    std::vector<double> trim_cp_uv, trim_cp_w;
+};
+bool extract_nurbs3d(const gwn_nurbs3d &in, NurbsPatches &out, std::string &err);
 // Clip the closed trim loops `in` of a patch's visible region to the half
 // x_dir <= c (low) or >= c of the unit square and map them to the half's
 // own unit square (trimclip.cpp).  false: the cut passes through a junction

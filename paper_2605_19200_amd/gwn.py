@@ -23,7 +23,8 @@ GWN_NCOUNTERS = len(COUNTER_NAMES)
 (GWN_I_SUMMARY, GWN_I_LEAVES, GWN_I_NODES, GWN_I_MOMENTS, GWN_I_UNCENTERED, GWN_I_COMPLEX, GWN_I_MULTIPOLE,
  GWN_I_FARBETA, GWN_I_LEAF_TRIMS) = range(9)
 
-EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_set_params",
+EXPORTED = ["gwn_default_params", "gwn_build2d", "gwn_build3d", "gwn_nurbs2d_extract", "gwn_nurbs3d_extract",
+            "gwn_set_params",
             "gwn_get_params", "gwn_query", "gwn_query_noalloc", "gwn_query_scratch_bytes",
             "gwn_query_batch", "gwn_query_counters", "gwn_model_bytes", "gwn_inspect", "gwn_profile",
             "gwn_profile_kernel", "gwn_free", "gwn_last_error"]
@@ -54,6 +55,13 @@ class gwn_nurbs2d(ctypes.Structure):
     _fields_ = [("n_curves", ctypes.c_int64), ("degree", ctypes.c_void_p), ("cp_offset", ctypes.c_void_p),
                 ("cp_xy", ctypes.c_void_p), ("cp_w", ctypes.c_void_p), ("knot_offset", ctypes.c_void_p),
                 ("knots", ctypes.c_void_p)]
+
+
+class gwn_nurbs3d(ctypes.Structure):
+    _fields_ = [("n_surfaces", ctypes.c_int64)] + [(f, ctypes.c_void_p) for f in (
+        "degree_u", "degree_v", "n_u", "n_v", "cp_offset", "cp_xyz", "cp_w", "knot_u_offset", "knots_u",
+        "knot_v_offset", "knots_v", "trim_offset", "trim_degree", "trim_cp_offset", "trim_cp_uv", "trim_cp_w",
+        "trim_knot_offset", "trim_knots")]
 
 
 class gwn_patches3d(ctypes.Structure):
@@ -87,6 +95,8 @@ def lib():
             ("gwn_build3d", [ctypes.POINTER(gwn_patches3d), ctypes.POINTER(gwn_params), ctypes.POINTER(vp)]),
             ("gwn_nurbs2d_extract", [ctypes.POINTER(gwn_nurbs2d), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                      vp, vp, vp, vp]),
+            ("gwn_nurbs3d_extract", [ctypes.POINTER(gwn_nurbs3d), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp, vp]),
             ("gwn_set_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_get_params", [vp, ctypes.POINTER(gwn_params)]),
             ("gwn_query", [vp, vp, i64, vp, vp, vp]),
@@ -200,6 +210,31 @@ def gwn_nurbs2d_extract(nurbs):
     _check(lib().gwn_nurbs2d_extract(ctypes.byref(c), ctypes.byref(ns), ctypes.byref(npt), _p(deg), _p(off),
                                      _p(xy), _p(w)))
     return Curves2D(deg, off, xy, w)
+
+
+def gwn_nurbs3d_extract(nurbs):
+    """Rational bicubic Bezier patches of a ``workloads.Nurbs3D`` as a
+    ``workloads.Patches3D`` (two calls of the C entry point: sizes, then the
+    arrays)."""
+    from .workloads import Patches3D
+    t = nurbs.trims
+    arrs = [_np(nurbs.degree_u, np.int32), _np(nurbs.degree_v, np.int32), _np(nurbs.n_u, np.int32),
+            _np(nurbs.n_v, np.int32), _np(nurbs.cp_offset, np.int64), _np(nurbs.cp_xyz, np.float64),
+            _np(nurbs.cp_w, np.float64), _np(nurbs.knot_u_offset, np.int64), _np(nurbs.knots_u, np.float64),
+            _np(nurbs.knot_v_offset, np.int64), _np(nurbs.knots_v, np.float64), _np(nurbs.trim_offset, np.int64),
+            _np(t.degree, np.int32), _np(t.cp_offset, np.int64), _np(t.cp_xy, np.float64), _np(t.cp_w, np.float64),
+            _np(t.knot_offset, np.int64), _np(t.knots, np.float64)]
+    c = gwn_nurbs3d(nurbs.n, *[_p(a) for a in arrs])
+    n, nt, nc = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    cnt = [ctypes.byref(n), ctypes.byref(nt), ctypes.byref(nc)]
+    _check(lib().gwn_nurbs3d_extract(ctypes.byref(c), *cnt, None, None, None, None, None, None, None))
+    if n.value == 0:
+        return Patches3D.from_list([])
+    out = [np.zeros((n.value, 16, 3)), np.zeros((n.value, 16)), np.zeros(n.value + 1, np.int64),
+           np.zeros(nt.value, np.int32), np.zeros(nt.value + 1, np.int64), np.zeros((nc.value, 2)),
+           np.zeros(nc.value)]
+    _check(lib().gwn_nurbs3d_extract(ctypes.byref(c), *cnt, *[_p(a) for a in out]))
+    return Patches3D(*out)
 
 
 def gwn_set_params(h, params: gwn_params):

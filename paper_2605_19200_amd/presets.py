@@ -64,13 +64,26 @@ MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125
 # most 64 near leaves per query their sum stays below 1e-6 even if every
 # leaf reached its tolerance (on the checked near-field pairs the errors
 # were ~3e-11).
-FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, precision=G.GWN_FP64)
+# Error-budgeted far test (far_tol: a factor per cluster from the estimated
+# size of its first two omitted harmonic degrees, instead of one beta for
+# all), order 6, one 128^3 launch of the bodies scene / 1M queries of the CAD
+# assembly, max |dw| on the committed oracle rows:
+#   uniform beta 5:  122.7 ms, 7.3e-8   |  1045 ms, 7.4e-8
+#   far_tol 1e-7:     98.5 ms, 3.9e-7   |   979 ms, 5.8e-7
+#   far_tol 3e-8:    107.3 ms, 1.3e-7
+#   far_tol 1e-8:    116.7 ms, 4.8e-8   |  1027 ms, 5.7e-8  (chosen)
+#   far_tol 1e-9:    144.5 ms, 8.6e-9   |  1087 ms, 9.8e-9
+#   order 4, far_tol 1e-8: 174.1 ms, 1.3e-7
+# The chosen budget is faster and more accurate than the uniform factor; the
+# CAD assembly's time is nearly all near field, so it gains less.
+FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, far_tol=1e-8, precision=G.GWN_FP64)
 # A reached leaf that passes the far test itself takes its own expansion
 # (leaf_far, the default): on the checked sets this halves the node-set work
 # per query (CAD assembly: 113k -> 53k integrand nodes) at the same error.
 # The paper's setting evaluates every reached leaf directly (Alg. 1).
 PAPER_ORDER_3D = dict(beta=16.0, taylor_order=2, leaf_far=0, eps_q=1e-8, precision=G.GWN_FP64)
-MIXED_3D = dict(beta=5.0, beta_mixed=3.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, precision=G.GWN_MIXED,
+MIXED_3D = dict(beta=5.0, beta_mixed=3.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, far_tol=1e-8,
+                precision=G.GWN_MIXED,
                 reclass_band=1e-2)
 
 

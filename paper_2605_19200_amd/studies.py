@@ -233,7 +233,7 @@ def order_beta_3d():
     rows = []
     for order in (0, 2, 4, 6):
         for beta in (2.0, 3.0, 5.0, 8.0, 16.0):
-            r = _model3d_rows(P, q, fx, presets.FP64_3D, taylor_order=order, beta=beta)
+            r = _model3d_rows(P, q, fx, presets.FP64_3D, taylor_order=order, beta=beta, far_tol=0.0)
             rows.append(dict(order=order, beta=beta, **r))
             _log(f"order_beta_3d bodies: order {order} beta {beta}: {r['ms']} ms, {r['oracle_max_abs_dw']:.2e}")
     out.append(dict(workload="bodies scene: 4096 trimmed patches, 128^3 grid; oracle rows: 512 grid + 512 "
@@ -243,7 +243,7 @@ def order_beta_3d():
     rows = []
     for order in (2, 4, 6):
         for beta in (3.0, 5.0, 8.0):
-            r = _model3d_rows(P, q, fx, presets.FP64_3D, taylor_order=order, beta=beta)
+            r = _model3d_rows(P, q, fx, presets.FP64_3D, taylor_order=order, beta=beta, far_tol=0.0)
             rows.append(dict(order=order, beta=beta, **r))
             _log(f"order_beta_3d cad: order {order} beta {beta}: {r['ms']} ms, {r['oracle_max_abs_dw']:.2e}")
     out.append(dict(workload="CAD assembly: 19,968 trimmed patches, 1M queries (half near-surface); oracle rows: "
@@ -291,7 +291,7 @@ def subdivision_3d():
         rows.append(dict(max_diag_frac=frac, **r))
         _log(f"subdivision_3d: {frac} -> {r['leaves']} leaves, {r['ms']} ms")
     return dict(study="subdivision_3d", workload="bodies scene: 4096 trimmed patches, 128^3 grid, FP64 form "
-                f"(order {presets.FP64_3D['taylor_order']}, beta {presets.FP64_3D['beta']})", rows=rows)
+                f"(order {presets.FP64_3D['taylor_order']}, far_tol {presets.FP64_3D['far_tol']:g})", rows=rows)
 
 
 STUDIES = dict(order_beta=order_beta, subdivision=subdivision, far_tol=far_tol, disagreement=disagreement,

@@ -159,6 +159,59 @@ class Nurbs2D:
 
 
 @dataclasses.dataclass
+class Nurbs3D:
+    """Trimmed NURBS surfaces (input of ``gwn.gwn_nurbs3d_extract``): degrees
+    1..3 per direction, clamped knot vectors, an n_u x n_v net per surface
+    (u-major), trim curves as 2D NURBS of degree 1..2 in the surface's
+    parameter domain."""
+    degree_u: np.ndarray        # int32[n]
+    degree_v: np.ndarray        # int32[n]
+    n_u: np.ndarray             # int32[n]
+    n_v: np.ndarray             # int32[n]
+    cp_offset: np.ndarray       # int64[n+1]
+    cp_xyz: np.ndarray          # float64[n_cp, 3]
+    cp_w: np.ndarray            # float64[n_cp]
+    knot_u_offset: np.ndarray   # int64[n+1]
+    knots_u: np.ndarray
+    knot_v_offset: np.ndarray   # int64[n+1]
+    knots_v: np.ndarray
+    trim_offset: np.ndarray     # int64[n+1]
+    trims: Nurbs2D              # all trim curves, surface after surface
+
+    @property
+    def n(self) -> int:
+        return int(self.degree_u.shape[0])
+
+    @staticmethod
+    def from_list(surfaces) -> "Nurbs3D":
+        """``surfaces``: iterable of (pu, pv, cp[n_u, n_v, 3], w[n_u, n_v],
+        U, V, trims) with ``trims`` a list of (degree, uv[k, 2], w[k], knots)
+        2D NURBS curves (empty = untrimmed)."""
+        pu, pv, nu, nv, off, xyz, w, kuo, ku, kvo, kv, toff, tr = ([], [], [], [], [0], [], [], [0], [], [0], [],
+                                                                    [0], [])
+        for p_u, p_v, cp, wt, U, V, trims in surfaces:
+            cp = np.asarray(cp, np.float64)
+            pu.append(int(p_u))
+            pv.append(int(p_v))
+            nu.append(cp.shape[0])
+            nv.append(cp.shape[1])
+            off.append(off[-1] + cp.shape[0] * cp.shape[1])
+            xyz.append(cp.reshape(-1, 3))
+            w.append(np.asarray(wt, np.float64).reshape(-1))
+            ku.append(np.asarray(U, np.float64).reshape(-1))
+            kv.append(np.asarray(V, np.float64).reshape(-1))
+            kuo.append(kuo[-1] + ku[-1].shape[0])
+            kvo.append(kvo[-1] + kv[-1].shape[0])
+            tr.extend(trims)
+            toff.append(toff[-1] + len(trims))
+        cat = (lambda a, shape: np.ascontiguousarray(np.concatenate(a)) if a else np.zeros(shape))
+        i32 = (lambda a: np.asarray(a, np.int32))
+        i64 = (lambda a: np.asarray(a, np.int64))
+        return Nurbs3D(i32(pu), i32(pv), i32(nu), i32(nv), i64(off), cat(xyz, (0, 3)), cat(w, (0,)), i64(kuo),
+                       cat(ku, (0,)), i64(kvo), cat(kv, (0,)), i64(toff), Nurbs2D.from_list(tr))
+
+
+@dataclasses.dataclass
 class Patches3D:
     cp_xyz: np.ndarray          # float64[n,16,3]
     cp_w: np.ndarray            # float64[n,16]

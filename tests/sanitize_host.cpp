@@ -1,6 +1,7 @@
 // The engine's host-side builders under AddressSanitizer and UBSan (test
 // infrastructure, compiled and run by tests/test_sanitize_host.py with g++
-// and no GPU).  Reads a case file of 2D curves, 2D NURBS and 3D patches
+// and no GPU).  Reads a case file of 2D curves, 2D NURBS, 3D patches, query
+// points (skipped here) and 3D NURBS surfaces
 // (arrays in a fixed order, each an int64 element count followed by the raw
 // little-endian values), then builds host-only models from them at several
 // subdivision thresholds, and prints one summary line per build.
@@ -101,6 +102,27 @@ int main(int argc, char **argv)
         auto tcoff = r.next<int64_t>();
         auto tuv = r.next<double>();
         auto tw = r.next<double>();
+        (void)r.next<double>();   // 2D and 3D query points: the oracle driver's
+        (void)r.next<double>();
+        // 3D NURBS surfaces
+        auto sdu = r.next<int32_t>();
+        auto sdv = r.next<int32_t>();
+        auto snu = r.next<int32_t>();
+        auto snv = r.next<int32_t>();
+        auto scoff = r.next<int64_t>();
+        auto sxyz = r.next<double>();
+        auto sw = r.next<double>();
+        auto skuo = r.next<int64_t>();
+        auto sku = r.next<double>();
+        auto skvo = r.next<int64_t>();
+        auto skv = r.next<double>();
+        auto stoff = r.next<int64_t>();
+        auto stdeg = r.next<int32_t>();
+        auto stcoff = r.next<int64_t>();
+        auto stuv = r.next<double>();
+        auto stw = r.next<double>();
+        auto stkoff = r.next<int64_t>();
+        auto stk = r.next<double>();
         std::fclose(f);
 
         gwn_curves2d c2{(int64_t)deg.size(), deg.data(), off.data(), xy.data(), w.data()};
@@ -129,6 +151,16 @@ int main(int argc, char **argv)
             return 1;
         }
         std::printf("nurbs: %zu segments\n", edeg.size());
+
+        gwn_nurbs3d n3{(int64_t)sdu.size(), sdu.data(), sdv.data(), snu.data(), snv.data(), scoff.data(),
+                       sxyz.data(), sw.data(), skuo.data(), sku.data(), skvo.data(), skv.data(), stoff.data(),
+                       stdeg.data(), stcoff.data(), stuv.data(), stw.data(), stkoff.data(), stk.data()};
+        NurbsPatches np3;
+        if (!extract_nurbs3d(n3, np3, nerr)) {
+            std::printf("nurbs3d: %s\n", nerr.c_str());
+            return 1;
+        }
+        std::printf("nurbs3d: %zu patches %zu trim curves\n", np3.cp_w.size() / 16, np3.trim_degree.size());
 
         const int64_t np = (int64_t)cw.size() / 16;
         gwn_patches3d c3{np, cp.data(), cw.data(), toff.data(), tdeg.data(), tcoff.data(), tuv.data(), tw.data()};

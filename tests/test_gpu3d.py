@@ -60,7 +60,7 @@ def test_sphere_all_direct(sphere, frac, near_tol):
     # the error-controlled near-field rule (the fixed node-set rules farther
     # out err by ~1e-9 per leaf, which at the preset's 0.25 adds to ~1e-8
     # over the many small leaves near q)
-    m = G.Model(sphere, presets.params(presets.FP64_3D, beta=1e8, max_diag_frac=frac, eps_q=1e-11,
+    m = G.Model(sphere, presets.params(presets.FP64_3D, beta=1e8, far_tol=0.0, max_diag_frac=frac, eps_q=1e-11,
                                        near_ratio=0.5))
     print(f"sphere all direct, max_diag_frac {frac}: {int(m.inspect(G.GWN_I_SUMMARY)[0][2])} leaves", flush=True)
     rng = W.Rng(41, "sph")
@@ -93,7 +93,7 @@ def test_sphere_fp64_form(sphere, oracle):
 def test_closed_forms_triangle_and_holed_plate():
     rng = W.Rng(43, "cf")
     A, B, C = np.array([[0, 0, 0], [1, 0.1, 0], [0.2, 1, 0.1]])
-    m = G.Model(patches((*bilinear_patch(A, B, C, C), [])), presets.params(presets.FP64_3D, beta=1e8))
+    m = G.Model(patches((*bilinear_patch(A, B, C, C), [])), presets.params(presets.FP64_3D, beta=1e8, far_tol=0.0))
     qs = rng.uniform((64, 3), -1, 1.5)
     w, _ = run(m, qs)
     ref = np.array([vos(A, B, C, q) for q in qs]) / (4 * math.pi)
@@ -101,7 +101,7 @@ def test_closed_forms_triangle_and_holed_plate():
     cp, wt = bilinear_patch((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0))
     c, R = (0.5, 0.45), 0.2
     m = G.Model(patches((cp, wt, W.square_trim() + W.circle_trim(c, R, ccw=False))),
-                presets.params(presets.FP64_3D, beta=1e8))
+                presets.params(presets.FP64_3D, beta=1e8, far_tol=0.0))
     hs = np.array([0.001, 0.05, 0.3, -0.2, -1e-5])
     q = np.stack([np.full(hs.shape, c[0]), np.full(hs.shape, c[1]), hs], 1)
     w, _ = run(m, q)
@@ -214,7 +214,7 @@ def test_error_decreases_with_order_3d(cfg3):
     P, q, qs, ref = cfg3
     errs = []
     for order in (0, 2, 4, 6):
-        m = G.Model(P, presets.params(presets.FP64_3D, beta=3.0, taylor_order=order))
+        m = G.Model(P, presets.params(presets.FP64_3D, beta=3.0, far_tol=0.0, taylor_order=order))
         w, _ = run(m, qs)
         errs.append(np.abs(w - ref).max())
         m.close()
@@ -240,6 +240,28 @@ def test_stretched_patch_near_field(cfg3, oracle):
     m = G.Model(P, presets.params(presets.FP64_3D))
     w, ins = run(m, q)
     check(w, ins, oracle.gwn3d(P, q))
+
+
+def test_far_budget_repack_on_device(cfg3):
+    """Changing far_tol on a device model rewrites the 3D cluster radii in
+    place: results equal a fresh build with the new setting bit for bit, in
+    both directions, and the budget keeps the preset's accuracy."""
+    P, q, qs, ref = cfg3
+    m = G.Model(P, presets.params(presets.FP64_3D))
+    assert presets.FP64_3D["far_tol"] > 0
+    w_budget, ins = run(m, qs)
+    check(w_budget, ins, ref)
+    m.set(far_tol=0.0)
+    w_uniform, _ = run(m, qs)
+    fresh = G.Model(P, presets.params(presets.FP64_3D, far_tol=0.0))
+    assert np.array_equal(w_uniform, run(fresh, qs)[0])
+    fresh.close()
+    assert not np.array_equal(w_uniform, w_budget)
+    m.set(far_tol=presets.FP64_3D["far_tol"])
+    assert np.array_equal(run(m, qs)[0], w_budget)
+    fb = m.inspect(G.GWN_I_FARBETA)[:, 0]
+    assert np.all(np.isfinite(fb)) and np.all(fb >= 1.5)
+    m.close()
 
 
 def test_device_lbvh_matches_host():

@@ -42,6 +42,8 @@ def case(tmp_path_factory):
     P3, _ = W.config3(grid=0)
     P4 = W.cad_assembly(4, n_bodies=2)
     P = P3.subset(np.arange(0, P3.n, 16)).concat(P4.subset(np.arange(0, P4.n, 4)))
+    from tests.test_nurbs3d import nurbs_cube
+    S3 = nurbs_cube(W.Rng(94, "sanitize-nurbs3d"))
     q2 = W.bbox_queries_uniform(W.Rng(92, "sanitize-q2"), *C.bbox(), 24)
     q3 = W.bbox_queries_uniform(W.Rng(93, "sanitize-q3"), *P.bbox(), 6)
     path = str(tmp_path_factory.mktemp("san") / "case.bin")
@@ -54,6 +56,14 @@ def case(tmp_path_factory):
         _arr(f, P.trim_degree, np.int32), _arr(f, P.trim_cp_offset, np.int64)
         _arr(f, P.trim_cp_uv, np.float64), _arr(f, P.trim_cp_w, np.float64)
         _arr(f, q2, np.float64), _arr(f, q3, np.float64)
+        S, T = S3, S3.trims
+        for a, dt in ((S.degree_u, np.int32), (S.degree_v, np.int32), (S.n_u, np.int32), (S.n_v, np.int32),
+                      (S.cp_offset, np.int64), (S.cp_xyz, np.float64), (S.cp_w, np.float64),
+                      (S.knot_u_offset, np.int64), (S.knots_u, np.float64), (S.knot_v_offset, np.int64),
+                      (S.knots_v, np.float64), (S.trim_offset, np.int64), (T.degree, np.int32),
+                      (T.cp_offset, np.int64), (T.cp_xy, np.float64), (T.cp_w, np.float64),
+                      (T.knot_offset, np.int64), (T.knots, np.float64)):
+            _arr(f, a, dt)
     return path, C, P, q2, q3
 
 
@@ -70,6 +80,7 @@ def test_host_builders_sanitized(case, tmp_path):
     lines = r.stdout.splitlines()
     assert sum(ln.startswith("2d ") for ln in lines) == 4 and sum(ln.startswith("3d ") for ln in lines) == 2
     assert any(ln.startswith("nurbs: ") and "segments" in ln for ln in lines)
+    assert any(ln.startswith("nurbs3d: ") and "patches" in ln for ln in lines)
 
 
 def test_oracle_sanitized(case, tmp_path, oracle):
