@@ -193,7 +193,28 @@ typedef struct {
                               nodes); 0 = every reached leaf is evaluated
                               directly, as in Alg. 1.  Default 1; 2D leaves
                               are always direct (the chord angle is exact)   */
-    int32_t reserved;      /* set to 0                                      */
+    int32_t wave_accept;   /* Q: 0 (default): each query takes a cluster as
+                              far by its own test, as in Alg. 1, so a query's
+                              value does not depend on the other queries of
+                              the call.  1: a cluster is taken as far only
+                              when every query of the wave (the 64
+                              neighbouring queries of the call's
+                              space-filling-curve order that share one
+                              traversal) passes its test, otherwise all of
+                              them descend: the far-field terms then run on
+                              full waves instead of a few lanes, and each
+                              query's accepted clusters are the same or
+                              smaller ones (same error bound per cluster).
+                              A query's value then depends on the queries
+                              that share its wave: a call repeats bit for
+                              bit, but the same point in another call (a
+                              subset, a split, another order of points
+                              that share a sort key, or another call size,
+                              which sets the queries per wave) may differ
+                              within the error budget.  Applies to the FP64
+                              tests (also the mixed form's FP64
+                              re-evaluation); the FP32 pass keeps per-query
+                              tests.                                       */
     double far_tol;        /* Q: error budget of the FP64 far test, per
                               accepted cluster.  0 (default): a cluster is
                               far when ||q - c|| > beta * r.  > 0: each

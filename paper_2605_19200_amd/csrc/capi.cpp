@@ -46,7 +46,7 @@ extern "C" void gwn_default_params(gwn_params *p)
     p->near_ratio = 0.25;
     p->eps_q = 1e-6;
     p->leaf_far = 1;
-    p->reserved = 0;
+    p->wave_accept = 0;
     p->far_tol = 0.0;
 }
 
@@ -64,6 +64,7 @@ static gwn_status check_query_params(int dim, const gwn_params *p)
     if (!(p->near_ratio >= 0) || !std::isfinite(p->near_ratio)) return fail(GWN_EINVAL, "bad near_ratio");
     if (!(p->eps_q > 0)) return fail(GWN_EINVAL, "eps_q must be > 0");
     if (p->leaf_far != 0 && p->leaf_far != 1) return fail(GWN_EINVAL, "leaf_far must be 0 or 1");
+    if (p->wave_accept != 0 && p->wave_accept != 1) return fail(GWN_EINVAL, "wave_accept must be 0 or 1");
     if (!(p->far_tol >= 0) || !std::isfinite(p->far_tol)) return fail(GWN_EINVAL, "far_tol must be finite and >= 0");
     return GWN_OK;
 }
@@ -98,6 +99,7 @@ void refresh_dev_params(Model &m)
     m.dev.eps_on = p.eps_on * m.diag;
     m.dev.near_ratio2 = p.near_ratio * p.near_ratio;
     m.dev.leaf_far = p.leaf_far;
+    m.dev.wave_accept = p.wave_accept;
     m.dev.eps_q = p.eps_q;
     m.dev.gl_n = p.gl_nodes;
 }
@@ -436,6 +438,7 @@ extern "C" gwn_status gwn_set_params(gwn_handle h, const gwn_params *params)
     p.leaf_far = params->leaf_far;
     p.eps_q = params->eps_q;
     p.far_tol = params->far_tol;
+    p.wave_accept = params->wave_accept;
     gwn_status s = check_query_params(h->m.dim, &p);
     if (s) return s;
     const gwn_params old = h->m.params;

@@ -169,6 +169,7 @@ struct DevModel {
     double eps_q;           // 3D near-field tolerance
     int32_t gl_n;           // 3D GL nodes
     int32_t leaf_far;       // 3D: far leaves by their own expansion (gwn_params)
+    int32_t wave_accept;    // FP64 far tests decided for the whole wave (gwn_params)
 };
 
 // ---------------------------------------------------------------------------

@@ -389,6 +389,8 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                     const double dx = qx - bb[0], dy = qy - bb[1];
                     const double d2 = dx * dx + dy * dy;
                     far = d2 > beta2 * bb[2];
+                    // wave acceptance: far only when every active lane is
+                    if (M.wave_accept && __ballot(far) != curmask) far = false;
                     if (far)
                         acc += M.order == kMaxOrder2D
                                    ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, bb[3], nodes[cur].m)
@@ -586,9 +588,10 @@ static gwn_status hip_err(hipError_t e, const char *what, std::string &err)
 // Queries per wave of a launch of n queries: a launch of fewer than 2^18
 // queries spreads them over up to 4096 waves (at least 8 queries each):
 // scattered queries share few nodes, so a wave's cost grows with its number
-// of queries, and more waves keep more of the 1024 SIMDs busy.  Each query's
-// value does not depend on its wave mates, so results are the same at any
-// spread.
+// of queries, and more waves keep more of the 1024 SIMDs busy.  With
+// per-query far tests a query's value does not depend on its wave mates, so
+// results are the same at any spread; with wave acceptance they are the
+// same for the same call.
 static int32_t queries_per_wave(int64_t n)
 {
     int32_t qpw = 64;
@@ -600,8 +603,9 @@ static int32_t queries_per_wave(int64_t n)
 // sort keys and row indices (double-buffered), the radix sort's temporary
 // storage and, in 3D, the near-field pass's per-slot records.  Nothing in it
 // needs to start at zero: every record is written before it is read.  The
-// sort orders the queries for coherent waves only (no value depends on the
-// order), so it takes the top 24 Morton bits (bits 24-47: 2^12 cells per
+// sort orders the queries for coherent waves (with per-query far tests no
+// value depends on the order; with wave acceptance the order decides which
+// queries decide together), so it takes the top 24 Morton bits (bits 24-47: 2^12 cells per
 // axis in 2D, 2^8 in 3D, far finer than a wave's footprint), or the top 18
 // for a launch under 2^16 queries, and the segment bits 48-53 only when the
 // launch has more than one segment: three 8-bit radix passes for one

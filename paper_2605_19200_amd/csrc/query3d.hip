@@ -183,10 +183,11 @@ __device__ __forceinline__ T multipole3d_fixed(T sx, T sy, T sz, const T *__rest
 }
 
 // Far test of node `cur` for one lane, adding its far-field term when the
-// test passes; true when it does.
+// test passes; true when it does.  With wave acceptance the FP64 test passes
+// only when it passes for every lane of `curmask` (the lanes at this node).
 template <bool F32>
 __device__ __forceinline__ bool far_term3d(const DevModel &M, const Node3 *__restrict__ nd, int cur, double qx,
-                                           double qy, double qz, double &acc_far)
+                                           double qy, double qz, double &acc_far, uint64_t curmask)
 {
     if (F32) {
         const float sx = nd->fc[0] - (float)qx, sy = nd->fc[1] - (float)qy, sz = nd->fc[2] - (float)qz;
@@ -201,7 +202,9 @@ __device__ __forceinline__ bool far_term3d(const DevModel &M, const Node3 *__res
     }
     const double sx = nd->c[0] - qx, sy = nd->c[1] - qy, sz = nd->c[2] - qz;
     const double r2 = sx * sx + sy * sy + sz * sz;
-    const bool far = r2 > M.beta2 * nd->r2;
+    bool far = r2 > M.beta2 * nd->r2;
+    // wave acceptance: far only when every active lane is
+    if (M.wave_accept && __ballot(far) != curmask) far = false;
     if (far) {
         const double *mp = (const double *)M.mpole + (size_t)cur * kMpoleStride;
         acc_far += M.order + 1 == kMaxL3 ? multipole3d_fixed<double, kMaxL3>(-sx, -sy, -sz, mp)
@@ -232,7 +235,7 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
         if (right < 0) {
             bool far = false;
             if (active && M.leaf_far) {
-                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far);
+                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far, curmask);
                 if (COUNT && far) { ctr.v[GWN_C_FAR]++; ctr.v[GWN_C_LEAVES]++; }
             }
             acc_leaf += leaf3d<COUNT>(M, nd, cur, qx, qy, qz, active && !far, ncnt, mylist, ctr);
@@ -240,7 +243,7 @@ __device__ double traverse3d(const DevModel &M, double qx, double qy, double qz,
             bool far = false;
             if (active) {
                 if (COUNT) ctr.v[GWN_C_NODES]++;
-                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far);
+                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far, curmask);
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }
             const uint64_t farmask = __ballot(active && far);

@@ -43,7 +43,7 @@ class gwn_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("reclass_band", ctypes.c_double), ("max_diag_frac", ctypes.c_double),
                 ("eps_on", ctypes.c_double), ("gl_nodes", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("near_ratio", ctypes.c_double), ("eps_q", ctypes.c_double), ("leaf_far", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("far_tol", ctypes.c_double)]
+                ("wave_accept", ctypes.c_int32), ("far_tol", ctypes.c_double)]
 
 
 class gwn_curves2d(ctypes.Structure):

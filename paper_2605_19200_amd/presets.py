@@ -30,16 +30,31 @@ order cap raised to 16 (far_tol 1e-8):
     order 14: 2.19 ms (runtime-order loop), 226 M
     order 16: 1.92 ms, 197 M node visits, max |dw| 5.7e-8  (chosen)
     order 16 at far_tol 2e-8: 1.84 ms, 1.0e-7
-FP64_2D therefore uses order 16, far_tol 1e-8 and max_diag_frac 0.0125
-(beta 3.25 stays the factor of the uniform test when far_tol is set to 0); PAPER_ORDER_2D keeps the paper's default order 2, uniform beta and
-10% threshold with the beta that meets the same bound.
+FP64_2D therefore used order 16, far_tol 1e-8 and max_diag_frac 0.0125
+(beta 3.25 stays the factor of the uniform test when far_tol is set to 0).
+Wave acceptance (wave_accept = 1: a cluster is taken as far only when every
+query of the wave passes its test, so the far-field terms run on full waves)
+then changes the trade-off; order 16, one 1024^2 call, max |dw| over the
+grid against the all-direct evaluation:
+    per-query tests, far_tol 1e-8: 1.70 ms, 5.7e-8, 197 M node visits
+    wave acceptance, far_tol 1e-8: 1.54 ms, 3.5e-8, 228 M node visits
+                             2e-8: 1.51 ms, 5.8e-8  (chosen: the error of
+                                   the per-query preset, 12 % faster)
+                             4e-8: 1.48 ms, 9.6e-8
+                             6e-8: 1.47 ms, 1.2e-7
+More nodes are opened (far queries descend with their near neighbours and
+take the same or smaller clusters, each within its budget), but the far
+terms no longer run on a few lanes at a time.
+PAPER_ORDER_2D keeps the paper's default order 2, uniform beta and 10%
+threshold with the beta that meets the same bound, and per-query tests.
 Mixed form (2D): FP32 far-field pass at beta_mixed = 2 (order 11: beyond
 it FP32 rounding dominates), then the FP64 form at order 12 on every query
 with |w - 0.5| < 1e-2.
 """
 from . import gwn as G
 
-FP64_2D = dict(beta=3.25, taylor_order=16, max_diag_frac=0.0125, far_tol=1e-8, precision=G.GWN_FP64)
+FP64_2D = dict(beta=3.25, taylor_order=16, max_diag_frac=0.0125, far_tol=2e-8, wave_accept=1,
+               precision=G.GWN_FP64)
 PAPER_ORDER_2D = dict(beta=64.0, taylor_order=2, precision=G.GWN_FP64)
 MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125, far_tol=1e-8,
                 precision=G.GWN_MIXED, reclass_band=1e-2)
@@ -71,12 +86,17 @@ MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125
 #   uniform beta 5:  122.7 ms, 7.3e-8   |  1045 ms, 7.4e-8
 #   far_tol 1e-7:     98.5 ms, 3.9e-7   |   979 ms, 5.8e-7
 #   far_tol 3e-8:    107.3 ms, 1.3e-7
-#   far_tol 1e-8:    116.7 ms, 4.8e-8   |  1027 ms, 5.7e-8  (chosen)
+#   far_tol 1e-8:    116.7 ms, 4.8e-8   |  1027 ms, 5.7e-8
 #   far_tol 1e-9:    144.5 ms, 8.6e-9   |  1087 ms, 9.8e-9
 #   order 4, far_tol 1e-8: 174.1 ms, 1.3e-7
-# The chosen budget is faster and more accurate than the uniform factor; the
-# CAD assembly's time is nearly all near field, so it gains less.
-FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, far_tol=1e-8, precision=G.GWN_FP64)
+# The budget is faster and more accurate than the uniform factor; the CAD
+# assembly's time is nearly all near field, so it gains less.  With wave
+# acceptance (as in 2D):
+#   far_tol 1e-8: 105.2 ms, 3.4e-8     |  1015 ms, 8.4e-8
+#   far_tol 2e-8:  99.7 ms, 6.4e-8     |  1010 ms, 8.3e-8  (chosen)
+#   far_tol 3e-8:  96.4 ms, 8.5e-8     |   993 ms, 1.2e-7
+FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, far_tol=2e-8, wave_accept=1,
+               precision=G.GWN_FP64)
 # A reached leaf that passes the far test itself takes its own expansion
 # (leaf_far, the default): on the checked sets this halves the node-set work
 # per query (CAD assembly: 113k -> 53k integrand nodes) at the same error.

@@ -28,16 +28,18 @@ producer to a loop running on its own thread and returns a
 * polls the events, hands the values back to their requests and releases
   their bytes.  A request is complete when its last piece is.
 
-Every query's value depends only on its own point and model: each lane makes
-its own far tests and sums its own terms in the left-first order of its own
-traversal, so a request's results equal those of a solo ``gwn_query``
-bitwise, whatever it was batched with (tested).
+Every query's value depends only on its own point and model: the server
+runs its models with per-query far tests (``wave_accept`` = 0, whatever the
+parameters given), each lane sums its own terms in the left-first order of
+its own traversal, so a request's results equal those of a solo
+``gwn_query`` bitwise, whatever it was batched with or cut into (tested).
 
 Latency of a request = completion time (when the loop sees its last event)
 minus its arrival time (the time it was offered to the loop).
 """
 from __future__ import annotations
 
+import ctypes
 import queue
 import threading
 import time
@@ -126,6 +128,13 @@ class Server:
     def add_model(self, geometry, params: G.gwn_params | None = None) -> int:
         if self._thread is not None:
             raise RuntimeError("add models before the first submit()")
+        # per-query far tests: a request's values then do not depend on how
+        # it is cut into pieces or on what shares its launch
+        if params is not None:
+            p = G.gwn_params()
+            ctypes.memmove(ctypes.byref(p), ctypes.byref(params), ctypes.sizeof(p))
+            p.wave_accept = 0
+            params = p
         m = G.Model(geometry, params)
         self.models.append(m)
         self.dims.append(m.dim)

@@ -30,7 +30,7 @@ def test_every_declared_symbol_is_exported():
 def test_default_params():
     p = G.gwn_default_params()
     assert p.beta == 2.0 and p.taylor_order == 2 and p.max_diag_frac == 0.1 and p.gl_nodes == 10
-    assert p.leaf_far == 1 and p.reserved == 0
+    assert p.leaf_far == 1 and p.wave_accept == 0
 
 
 def host_params(**kw):

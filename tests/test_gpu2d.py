@@ -57,13 +57,23 @@ def test_config1_fp64_form(cfg1, preset):
 
 
 def test_ragged_sizes_bitwise(cfg1):
+    """Per-query far tests (wave_accept = 0): a query's value does not depend
+    on the rest of the call.  With wave acceptance a prefix of the call may
+    differ within the FP64 bound, and the same call repeats bit for bit."""
     curves, q, ref = cfg1
-    m = G.Model(curves, presets.params(presets.FP64_2D))
+    m = G.Model(curves, presets.params(presets.FP64_2D, wave_accept=0))
     full, _ = run(m, q)
     for n in [1, 2, 63, 64, 65, 255, 257, 1000]:
         w, ins = run(m, q[:n])
         assert np.array_equal(w, full[:n]), n
         check(w, ins, ref[:n])
+    m.set(wave_accept=1)
+    full1, _ = run(m, q)
+    assert np.array_equal(run(m, q)[0], full1)
+    for n in [1, 63, 65, 1000]:
+        w, ins = run(m, q[:n])
+        check(w, ins, ref[:n])
+        assert np.array_equal(run(m, q[:n])[0], w), n
     out = torch.empty(0, dtype=torch.float64, device="cuda")
     G.gwn_query(m.h, dev(np.zeros((0, 2))), out, None)
     torch.cuda.synchronize()
@@ -77,7 +87,7 @@ def test_sort_sizes_duplicates_and_order(cfg1):
     depend on the order of the points (a shuffled launch gives the same
     bits)."""
     curves, q, _ = cfg1
-    m = G.Model(curves, presets.params(presets.FP64_2D))
+    m = G.Model(curves, presets.params(presets.FP64_2D, wave_accept=0))
     rng = W.Rng(27, "sort")
     lo, hi = curves.bbox()
     for n in [2, 3, 4095, 4096, 4097, 8193, 65535, 65536, 70001]:
@@ -239,7 +249,7 @@ def test_overlapping_polygons(oracle, k):
 def test_batch_bitwise_equals_solo(cfg1, cfg2):
     c1, q1, _ = cfg1
     c2, q2, _ = cfg2
-    m1 = G.Model(c1, presets.params(presets.FP64_2D))
+    m1 = G.Model(c1, presets.params(presets.FP64_2D, wave_accept=0))
     m2 = G.Model(c2, presets.params(presets.MIXED_2D))
     s1, _ = run(m1, q1)
     s2, _ = run(m2, q2)
@@ -270,6 +280,29 @@ def test_error_decreases_with_order(cfg2):
     assert errs[0] < 0.5
     for p in range(8):
         assert errs[p + 1] < errs[p], errs
+
+
+def test_wave_acceptance(cfg2):
+    """wave_accept = 1 takes a cluster as far only when every query of the
+    wave passes its test: within the FP64 bound against the oracle, within
+    2e-7 of the per-query tests, repeatable bit for bit, and it visits more
+    nodes (the far queries descend with their neighbours)."""
+    curves, q, ref = cfg2
+    m = G.Model(curves, presets.params(presets.FP64_2D, wave_accept=0))
+    w0, _ = run(m, q)
+    qd = dev(q)
+    c0 = m.counters(qd)
+    m.set(wave_accept=1)
+    w1, ins1 = run(m, q)
+    check(w1, ins1, ref)
+    assert np.abs(w1 - w0).max() <= 2e-7
+    assert np.array_equal(run(m, q)[0], w1)
+    assert m.counters(qd)["nodes"] > c0["nodes"]
+    p = G.gwn_get_params(m.h)
+    p.wave_accept = 2
+    with pytest.raises(G.GwnError):
+        G.gwn_set_params(m.h, p)
+    m.close()
 
 
 def test_counters(cfg1):

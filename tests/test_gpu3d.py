@@ -132,7 +132,7 @@ def test_config3_full_grid_subset_consistent(cfg3):
     no query of the grid hits a stack or near-field slot limit (NaN).  (The
     holed bodies are not closed, so w is not confined to [0, 1].)"""
     P, q, qs, ref = cfg3
-    m = G.Model(P, presets.params(presets.FP64_3D))
+    m = G.Model(P, presets.params(presets.FP64_3D, wave_accept=0))
     w_full, _ = run(m, q)
     assert np.all(np.isfinite(w_full))
     idx = W.Rng(44, "s3").permutation(q.shape[0])[:96]
@@ -181,7 +181,7 @@ def test_scale_invariance_3d(cfg4, scale):
 
 def test_batch_bitwise_3d(cfg4, sphere):
     P, qs, _ = cfg4
-    m1 = G.Model(P, presets.params(presets.FP64_3D))
+    m1 = G.Model(P, presets.params(presets.FP64_3D, wave_accept=0))
     m2 = G.Model(sphere, presets.params(presets.MIXED_3D))
     q2 = W.Rng(46, "b").uniform((100, 3), -1.2, 1.2)
     s1, _ = run(m1, qs)
@@ -201,7 +201,7 @@ def test_empty_and_ragged_3d(sphere):
     m = G.Model(W.Patches3D.from_list([]), presets.params(presets.FP64_3D))
     w, _ = run(m, np.ones((5, 3)))
     assert np.all(w == 0)
-    m = G.Model(sphere, presets.params(presets.FP64_3D))
+    m = G.Model(sphere, presets.params(presets.FP64_3D, wave_accept=0))
     q = W.Rng(47, "r").uniform((200, 3), -1.5, 1.5)
     full, _ = run(m, q)
     for n in [1, 63, 65, 129]:

@@ -37,7 +37,7 @@ def stacked_planes(k=80, gap=1e-3):
 
 def test_overflow_reported_once_then_cleared():
     P = stacked_planes()
-    m = G.Model(P, presets.params(presets.FP64_3D, max_diag_frac=0.0))
+    m = G.Model(P, presets.params(presets.FP64_3D, max_diag_frac=0.0, wave_accept=0))
     q_bad = np.array([[0.5, 0.5, 0.0395]])
     q_ok = np.array([[5.0, 5.0, 5.0], [0.5, 0.5, -3.0], [0.2, 0.7, 2.0]])
     print("overflow test: stacked planes, 1 overflowing + 3 plain queries", flush=True)
@@ -121,7 +121,7 @@ def test_served_overflow_stays_in_its_request():
     srv.close()
     assert np.isnan(wa[0]) and np.isfinite(wa[1])
     assert srv.overflow_reports == 1
-    m = G.Model(P, presets.params(presets.FP64_3D, max_diag_frac=0.0))
+    m = G.Model(P, presets.params(presets.FP64_3D, max_diag_frac=0.0, wave_accept=0))   # as served
     w_ref, _ = run(m, q_ok)
     assert np.array_equal(wb, w_ref)
     m.close()
