@@ -182,6 +182,7 @@ def bench3d() -> dict:
         m.query(pts[:4096])
         dt, trav, near, _, _, flagged = _query3d_timed(G, m, pts)
         out[name] = {"queries_per_s": q.shape[0] / dt, "ms": dt * 1e3, "beta": pre["beta"],
+                     "far_tol": pre.get("far_tol", 0.0), "wave_accept": pre.get("wave_accept", 0),
                      "k_trav3d_ms": trav, "k_near3d_ms": near, "flagged_rows": flagged,
                      "leaves": int(m.inspect(G.GWN_I_SUMMARY)[0][2]), "resident_bytes": int(m.bytes()[0])}
         if name == "fp64":
@@ -483,6 +484,7 @@ def main():
                                f"{curves.n} rational Bezier curves (degree 2-3), {args.grid}x{args.grid} grid",
                    "queries": n, "curves": curves.n, "beta": presets.FP64_2D["beta"],
                    "far_tol": presets.FP64_2D.get("far_tol", 0.0),
+                   "wave_accept": presets.FP64_2D.get("wave_accept", 0),
                    "taylor_order": presets.FP64_2D["taylor_order"],
                    "max_diag_frac": presets.FP64_2D.get("max_diag_frac", 0.1), "leaves": n_leaves,
                    "build_s": round(build_s, 3)},
