@@ -354,6 +354,11 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
     const float qxf = (float)qx, qyf = (float)qy;
     const double beta2 = F32 ? M.beta2_mixed : M.beta2;
     const float beta2f = (float)M.beta2_mixed;
+    // read once: inside the loop each use would be a scalar load and a wait
+    // per node (the loop's LDS stores keep the compiler from hoisting them)
+    const int order = M.order;
+    const bool wave_accept = M.wave_accept != 0;
+    const double eps_on = M.eps_on;
     double acc = 0.0;      // far-field terms, in radians
     AngleAcc A;            // direct (chord) angles
     angle_init(A);
@@ -370,7 +375,7 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
         const float ff[4] = {hd->f[0], hd->f[1], hd->f[2], hd->f[3]};
         const bool active = (curmask >> lane) & 1;
         if (right < 0) {
-            if (active) leaf2d<COUNT>(hd, bb, ff, prims, qx, qy, qxf, qyf, M.eps_on, A, ctr, overflow);
+            if (active) leaf2d<COUNT>(hd, bb, ff, prims, qx, qy, qxf, qyf, eps_on, A, ctr, overflow);
         } else {
             bool far = false;
             if (active) {
@@ -380,23 +385,23 @@ __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t m
                     const float d2 = dx * dx + dy * dy;
                     far = d2 > beta2f * ff[2];
                     if (far)
-                        acc += M.order >= kMaxOrder2D - 1
+                        acc += order >= kMaxOrder2D - 1
                                    ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, ff[3], nodes[cur].fm)
-                               : M.order >= kMixedOrder2D
+                               : order >= kMixedOrder2D
                                    ? (double)taylor2d_fixed<float, kMixedOrder2D>(dx, dy, d2, ff[3], nodes[cur].fm)
-                                   : (double)taylor2d<float>(dx, dy, d2, ff[3], nodes[cur].fm, M.order);
+                                   : (double)taylor2d<float>(dx, dy, d2, ff[3], nodes[cur].fm, order);
                 } else {
                     const double dx = qx - bb[0], dy = qy - bb[1];
                     const double d2 = dx * dx + dy * dy;
                     far = d2 > beta2 * bb[2];
                     // wave acceptance: far only when every active lane is
-                    if (M.wave_accept && __ballot(far) != curmask) far = false;
+                    if (wave_accept && __ballot(far) != curmask) far = false;
                     if (far)
-                        acc += M.order == kMaxOrder2D
+                        acc += order == kMaxOrder2D
                                    ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, bb[3], nodes[cur].m)
-                               : M.order == kMixedOrder2D + 1
+                               : order == kMixedOrder2D + 1
                                    ? taylor2d_fixed<double, kMixedOrder2D + 1>(dx, dy, d2, bb[3], nodes[cur].m)
-                                   : taylor2d<double>(dx, dy, d2, bb[3], nodes[cur].m, M.order);
+                                   : taylor2d<double>(dx, dy, d2, bb[3], nodes[cur].m, order);
                 }
                 if (COUNT && far) ctr.v[GWN_C_FAR]++;
             }
@@ -605,11 +610,12 @@ static int32_t queries_per_wave(int64_t n)
 // needs to start at zero: every record is written before it is read.  The
 // sort orders the queries for coherent waves (with per-query far tests no
 // value depends on the order; with wave acceptance the order decides which
-// queries decide together), so it takes the top 24 Morton bits (bits 24-47: 2^12 cells per
-// axis in 2D, 2^8 in 3D, far finer than a wave's footprint), or the top 18
-// for a launch under 2^16 queries, and the segment bits 48-53 only when the
-// launch has more than one segment: three 8-bit radix passes for one
-// segment instead of seven.
+// queries decide together), so it takes the top Morton bits down to 2^8
+// cells per axis (2D bits 32-47, 3D bits 24-47: a cell holds a few of a
+// full grid's queries), or the top 18 bits for a launch under 2^16 queries,
+// and the segment bits 48-53 only when the launch has more than one
+// segment: two (2D) or three (3D) 8-bit radix passes for one segment
+// instead of seven.
 struct ScratchPlan {
     size_t keys = 0, vals = 0, temp = 0, temp_bytes = 0;
     NearBytes near;
@@ -621,7 +627,7 @@ static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 static hipError_t plan_scratch(int dim, int64_t n, int64_t slots, hipStream_t stream, ScratchPlan &P)
 {
-    P.sort_lo = n < (1 << 16) ? 30 : 24;
+    P.sort_lo = n < (1 << 16) ? 30 : dim == 2 ? 32 : 24;
     P.temp_bytes = radix_temp_bytes(n);
     (void)stream;
     P.keys = al256(sizeof(uint64_t) * n);

@@ -57,8 +57,25 @@ struct NearScratch {
 // Direct solid angle of one leaf at q by its precomputed node set, chosen by
 // distance / half-diagonal ratio (finest near, coarsest far).  A leaf within
 // near_ratio of its diagonal is recorded for the near-field pass instead.
+// The model fields the traversal reads at every node, copied to registers
+// once: read through the model inside the loop, each would be a scalar load
+// and a wait per node (the loop's LDS stores keep the compiler from hoisting
+// them).
+struct TravParams {
+    const void *mpole, *fmpole, *qnodes;
+    double beta2, near_ratio2;
+    float beta2_mixed;
+    int order, wave_accept, leaf_far;
+};
+
+__device__ __forceinline__ TravParams trav_params(const DevModel &M)
+{
+    return TravParams{M.mpole, M.fmpole, M.qnodes, M.beta2, M.near_ratio2, (float)M.beta2_mixed,
+                      M.order, M.wave_accept, M.leaf_far};
+}
+
 template <bool COUNT>
-__device__ double leaf3d(const DevModel &M, const Node3 *__restrict__ nd, int cur, double qx, double qy, double qz,
+__device__ double leaf3d(const TravParams &M, const Node3 *__restrict__ nd, int cur, double qx, double qy, double qz,
                          bool active, int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
     const double dx = fmax(fmax(nd->t[0] - qx, qx - nd->t[3]), 0.0);
@@ -186,13 +203,13 @@ __device__ __forceinline__ T multipole3d_fixed(T sx, T sy, T sz, const T *__rest
 // test passes; true when it does.  With wave acceptance the FP64 test passes
 // only when it passes for every lane of `curmask` (the lanes at this node).
 template <bool F32>
-__device__ __forceinline__ bool far_term3d(const DevModel &M, const Node3 *__restrict__ nd, int cur, double qx,
+__device__ __forceinline__ bool far_term3d(const TravParams &M, const Node3 *__restrict__ nd, int cur, double qx,
                                            double qy, double qz, double &acc_far, uint64_t curmask)
 {
     if (F32) {
         const float sx = nd->fc[0] - (float)qx, sy = nd->fc[1] - (float)qy, sz = nd->fc[2] - (float)qz;
         const float r2 = sx * sx + sy * sy + sz * sz;
-        const bool far = r2 > (float)M.beta2_mixed * nd->fr2;
+        const bool far = r2 > M.beta2_mixed * nd->fr2;
         if (far) {
             const float *mp = (const float *)M.fmpole + (size_t)cur * kMpoleStride;
             acc_far += M.order + 1 == kMaxL3 ? (double)multipole3d_fixed<float, kMaxL3>(-sx, -sy, -sz, mp)
@@ -218,16 +235,17 @@ __device__ __forceinline__ bool far_term3d(const DevModel &M, const Node3 *__res
 // far-field expansion, like a cluster; the rest of the reached leaves are
 // evaluated directly (node sets, or recorded for the near-field pass).
 template <bool F32, bool COUNT>
-__device__ double traverse3d(const DevModel &M, double qx, double qy, double qz, uint64_t mask, StackLDS &S, int w,
-                             int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
+__device__ double traverse3d(const DevModel &Mdl, double qx, double qy, double qz, uint64_t mask, StackLDS &S,
+                             int w, int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
-    const Node3 *__restrict__ nodes = (const Node3 *)M.nodes;
+    const Node3 *__restrict__ nodes = (const Node3 *)Mdl.nodes;
+    const TravParams M = trav_params(Mdl);
     const int lane = lane_id();
     double acc_far = 0.0, acc_leaf = 0.0;
     int cur = 0;
     uint64_t curmask = mask;
     int sp = 0;
-    if (M.n_nodes == 0) return 0.0;
+    if (Mdl.n_nodes == 0) return 0.0;
     while (true) {
         const Node3 *nd = nodes + cur;
         const int right = nd->right;
