@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 
-SOURCES = ["capi.cpp", "tree.cpp", "build2d.cpp", "build3d.cpp", "trimclip.cpp", "nurbs.cpp", "moments2d.hip", "lbvh.hip", "radix.hip",
+SOURCES = ["capi.cpp", "tree.cpp", "build2d.cpp", "build3d.cpp", "trimclip.cpp", "nurbs.cpp", "moments2d.hip", "lbvh.hip", "radix.hip", "quad3d.hip",
            "query.hip", "query3d.hip"]
 
 

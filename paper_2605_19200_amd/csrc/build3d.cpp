@@ -507,7 +507,50 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         scatter(gx.data(), gw.data(), g, gx.data(), gw.data(), g,
                 [&](const QNode3 &node, double) { mpole_add_node(node.x, node.n, cl, kMaxLTail3, nl_out); });
     };
-    {
+    // A model built for a device runs the same quadrature there (quad3d.hip)
+    // and keeps its node sets in device memory; a host-only model runs it on
+    // up to 16 host threads.
+    const bool on_device = p->device >= 0 && nl > 0;
+    LeafQuad3 dq;
+    if (on_device) {
+        std::vector<double> nets(64 * (size_t)nl), box(6 * (size_t)nl), lnd;
+        std::vector<Trim3> curves;
+        std::vector<int64_t> coff(1, 0);
+        for (int li = 0; li < nl; ++li) {
+            const Patch &pt = leaves[li];
+            std::memcpy(&nets[64 * (size_t)li], pt.h, sizeof(pt.h));
+            patch_aabb(pt, &LO[3 * li], &HI[3 * li]);
+            for (int a = 0; a < 3; ++a) {
+                box[6 * (size_t)li + a] = LO[3 * li + a];
+                box[6 * (size_t)li + 3 + a] = HI[3 * li + a];
+            }
+            if (pt.trims.empty()) {
+                Trim3 e;
+                std::memset(&e, 0, sizeof e);
+                const double P[3][3] = {{1, 0, 1}, {1, 0.5, 1}, {1, 1, 1}};
+                for (int j = 0; j < 3; ++j)
+                    for (int q = 0; q < 3; ++q) e.h[3 * j + q] = P[j][q];
+                curves.push_back(e);
+            } else {
+                curves.insert(curves.end(), pt.trims.begin(), pt.trims.end());
+            }
+            coff.push_back((int64_t)curves.size());
+        }
+        double rx[4][kMaxQuadRule] = {}, rw[4][kMaxQuadRule] = {};
+        int rn[4];
+        for (int r = 0; r < 3; ++r) {
+            rn[r] = kLeafRules[r];
+            std::copy(lx[r].begin(), lx[r].end(), rx[r]);
+            std::copy(lw[r].begin(), lw[r].end(), rw[r]);
+        }
+        rn[3] = g;
+        std::copy(gx.begin(), gx.end(), rx[3]);
+        std::copy(gw.begin(), gw.end(), rw[3]);
+        const gwn_status s = leafquad3d_moments(p->device, nets, curves, coff, box, rx, rw, rn, dq, U, Wt, WC, LC,
+                                                lnd, qcount, err);
+        if (s != GWN_OK) return s;
+        std::memcpy(LN.data(), lnd.data(), lnd.size() * sizeof(double));
+    } else {
         const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
         const int per = (nl + nthreads - 1) / nthreads;
         std::vector<std::thread> pool;
@@ -523,24 +566,49 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
         err = "BVH depth " + std::to_string(m.tree.depth) + " exceeds the traversal stack";
         return GWN_EOVERFLOW;
     }
-    // multipole up-sweep: children follow their parent in DFS order, so a
-    // reverse sweep sees both children first; each is translated to the
-    // parent's centroid.  Stored scaled by 1/r^(l+1) (r = AABB half
-    // diagonal), which keeps the FP32 mirror in range.
+    // multipole up-sweep: each node's moments are its children's (or, for a
+    // leaf, its own) translated to the node's centroid.  The nodes of one
+    // depth are independent, so the sweep runs depth by depth from the
+    // deepest, each depth over host threads.  Stored scaled by 1/r^(l+1)
+    // (r = AABB half diagonal), which keeps the FP32 mirror in range.
     {
         const size_t nn = m.tree.nodes.size();
         std::vector<cplx> NN(nn * kMpoleTermsTail, cplx(0, 0));
-        for (size_t ii = nn; ii-- > 0;) {
+        std::vector<int> depth(nn, 0);
+        int max_depth = 0;
+        for (size_t ii = 0; ii < nn; ++ii) {   // a parent precedes its children
             const HostNode &h = m.tree.nodes[ii];
-            cplx *dst = &NN[ii * kMpoleTermsTail];
+            if (!h.is_leaf) depth[ii + 1] = depth[h.right] = depth[ii] + 1;
+            max_depth = std::max(max_depth, depth[ii]);
+        }
+        std::vector<std::vector<int>> level(max_depth + 1);
+        for (size_t ii = 0; ii < nn; ++ii) level[depth[ii]].push_back((int)ii);
+        auto up = [&](int ii) {
+            const HostNode &h = m.tree.nodes[ii];
+            cplx *dst = &NN[(size_t)ii * kMpoleTermsTail];
             if (h.is_leaf) {
                 mpole_translate(&LN[(size_t)h.leaf * kMpoleTermsTail], &LC[3 * (size_t)h.leaf], h.c, kMaxLTail3,
                                 dst);
             } else {
                 const HostNode &a = m.tree.nodes[ii + 1], &b = m.tree.nodes[h.right];
-                mpole_translate(&NN[(ii + 1) * kMpoleTermsTail], a.c, h.c, kMaxLTail3, dst);
+                mpole_translate(&NN[(size_t)(ii + 1) * kMpoleTermsTail], a.c, h.c, kMaxLTail3, dst);
                 mpole_translate(&NN[(size_t)h.right * kMpoleTermsTail], b.c, h.c, kMaxLTail3, dst);
             }
+        };
+        const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+        for (int d = max_depth; d >= 0; --d) {
+            const std::vector<int> &lv = level[d];
+            const int nt = std::min<int>(nthreads, (int)lv.size() / 64 + 1);
+            if (nt == 1) {
+                for (int ii : lv) up(ii);
+                continue;
+            }
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nt; ++t)
+                pool.emplace_back([&, t] {
+                    for (size_t k = t; k < lv.size(); k += nt) up(lv[k]);
+                });
+            for (auto &th : pool) th.join();
         }
         // per node, the largest magnitude of each degree's term at unit
         // distance over kTailDirs directions (a Fibonacci lattice of the
@@ -595,6 +663,15 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
     m.qnodes.clear();
     m.leaf_q_begin.clear();
     m.leaf_q_count.clear();
+    m.leaf_q_rules.clear();
+    {   // hundreds of MB of node sets: one allocation instead of regrowth
+        size_t tot = 0;
+        for (const auto &v : qn) tot += v.size();
+        m.qnodes.reserve(tot);
+        m.leaf_h.reserve(64 * (size_t)nl);
+    }
+    std::vector<int64_t> qbase(on_device ? nl : 0);
+    int64_t qtotal = 0;
     for (auto &nd : m.tree.nodes)
         if (nd.is_leaf) {
             const int src = nd.leaf;
@@ -607,11 +684,20 @@ gwn_status build3d_host(const gwn_patches3d *c, const gwn_params *p, Model &m, s
             m.leaf_trim_begin.push_back((int32_t)m.trims.size());
             m.leaf_trim_count.push_back((int32_t)pt.trims.size());
             m.trims.insert(m.trims.end(), pt.trims.begin(), pt.trims.end());
-            m.leaf_q_begin.push_back((int64_t)m.qnodes.size());
-            m.leaf_q_count.push_back((int64_t)qn[src].size());
+            const int64_t cnt = on_device ? (int64_t)qcount[src][0] + qcount[src][1] + qcount[src][2]
+                                          : (int64_t)qn[src].size();
+            m.leaf_q_begin.push_back(qtotal);
+            m.leaf_q_count.push_back(cnt);
             m.leaf_q_rules.push_back(qcount[src]);
-            m.qnodes.insert(m.qnodes.end(), qn[src].begin(), qn[src].end());
+            if (on_device) qbase[src] = qtotal;
+            else m.qnodes.insert(m.qnodes.end(), qn[src].begin(), qn[src].end());
+            qtotal += cnt;
         }
+    if (on_device) {
+        const gwn_status s = leafquad3d_nodes(dq, qbase, qtotal, &m.d_qnodes, err);
+        if (s != GWN_OK) return s;
+        m.n_qnodes_dev = qtotal;
+    }
     return GWN_OK;
 }
 

@@ -28,6 +28,8 @@ static gwn_status hip_fail(hipError_t e, const char *what)
 
 struct gwn_model {
     Model m;
+    // device node sets of a build that never reached the upload
+    ~gwn_model() { if (m.d_qnodes) (void)hipFree(m.d_qnodes); }
 };
 
 extern "C" void gwn_default_params(gwn_params *p)
@@ -214,7 +216,9 @@ gwn_status upload_model(Model &m, std::string &err)
         src[0] = n3.data(); bytes[0] = n3.size() * sizeof(Node3);
         src[1] = p3.data(); bytes[1] = p3.size() * sizeof(Prim3);
         src[2] = m.trims.data(); bytes[2] = m.trims.size() * sizeof(Trim3);
-        src[3] = m.qnodes.data(); bytes[3] = m.qnodes.size() * sizeof(QNode3);
+        // node sets: host vector, or (device build) already in device memory
+        src[3] = m.d_qnodes ? nullptr : m.qnodes.data();
+        bytes[3] = (m.d_qnodes ? (size_t)m.n_qnodes_dev : m.qnodes.size()) * sizeof(QNode3);
         fmp.assign(m.mpole.begin(), m.mpole.end());
         src[4] = m.mpole.data(); bytes[4] = m.mpole.size() * sizeof(double);
         src[5] = fmp.data(); bytes[5] = fmp.size() * sizeof(float);
@@ -224,17 +228,28 @@ gwn_status upload_model(Model &m, std::string &err)
     for (int k = 0; k < 7; ++k) off[k + 1] = align_up(off[k] + bytes[k], 256);
     size_t total = std::max<size_t>(off[7], 256);
     void *arena = nullptr;
+    auto drop_dev_qnodes = [&] {
+        if (m.d_qnodes) (void)hipFree(m.d_qnodes);
+        m.d_qnodes = nullptr;
+    };
     e = hipMalloc(&arena, total);
-    if (e != hipSuccess) { err = std::string("hipMalloc arena: ") + hipGetErrorString(e); return GWN_ENOMEM; }
+    if (e != hipSuccess) {
+        drop_dev_qnodes();
+        err = std::string("hipMalloc arena: ") + hipGetErrorString(e);
+        return GWN_ENOMEM;
+    }
     for (int k = 0; k < 7; ++k)
         if (bytes[k]) {
-            e = hipMemcpy((char *)arena + off[k], src[k], bytes[k], hipMemcpyHostToDevice);
+            e = src[k] ? hipMemcpy((char *)arena + off[k], src[k], bytes[k], hipMemcpyHostToDevice)
+                       : hipMemcpy((char *)arena + off[k], m.d_qnodes, bytes[k], hipMemcpyDeviceToDevice);
             if (e != hipSuccess) {
                 (void)hipFree(arena);
+                drop_dev_qnodes();
                 err = std::string("hipMemcpy arena: ") + hipGetErrorString(e);
                 return GWN_EHIP;
             }
         }
+    drop_dev_qnodes();
     int32_t *flag = nullptr;
     e = hipMalloc((void **)&flag, 256);
     if (e == hipSuccess) e = hipMemset(flag, 0, 256);

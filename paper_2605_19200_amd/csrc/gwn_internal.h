@@ -231,7 +231,9 @@ struct Model {
     // 3D only
     std::vector<Trim3> trims;
     std::vector<int32_t> leaf_trim_begin, leaf_trim_count;
-    std::vector<QNode3> qnodes;
+    std::vector<QNode3> qnodes;       // 3D node sets of a host build
+    void *d_qnodes = nullptr;          // 3D node sets of a device build (device memory until upload)
+    int64_t n_qnodes_dev = 0;
     std::vector<int64_t> leaf_q_begin, leaf_q_count;
     std::vector<std::array<int, 3>> leaf_q_rules;
     std::vector<double> mpole;        // 3D: per node kMpoleStride doubles (multipole3d.h)
@@ -284,6 +286,33 @@ struct NurbsPatches {
     std::vector<double> trim_cp_uv, trim_cp_w;
 };
 bool extract_nurbs3d(const gwn_nurbs3d &in, NurbsPatches &out, std::string &err);
+// Device leaf quadrature of a 3D model (quad3d.hip).  leafquad3d_moments
+// uploads the leaves (nets: 64 doubles per leaf, the homogeneous bicubic net
+// [i][j][wx, wy, wz, w]; curves: each leaf's boundary curves, its trims or
+// the edge u = 1 of an untrimmed square, leaf l's at [coff[l], coff[l+1]);
+// box: lo[3], hi[3] per leaf) and returns, per leaf in that order, the
+// uncentred moments U (n_moments(3) each), area Wt, area-weighted centroid
+// sums WC, centroid LC, multipole moments LN about LC (kMpoleTermsTail
+// (re, im) pairs each) and the sizes of the three node-set rules.  Rule r of
+// rule_x / rule_w has rule_n[r] nodes: 0-2 the node-set rules, 3 the moment
+// rule.  leafquad3d_nodes then writes the node sets of leaf l at qbase[l]
+// of a new device array of `total` QNode3 (returned in *out, owned by the
+// caller).  The uploaded leaves stay in `st` between the two calls.
+constexpr int kMaxQuadRule = 32;
+struct LeafQuad3 {
+    int device = -1;
+    int64_t nl = 0;
+    void *nets = nullptr, *curves = nullptr, *coff = nullptr, *tab = nullptr, *counts = nullptr;
+    ~LeafQuad3();
+};
+gwn_status leafquad3d_moments(int device, const std::vector<double> &nets, const std::vector<Trim3> &curves,
+                              const std::vector<int64_t> &coff, const std::vector<double> &box,
+                              const double (*rule_x)[kMaxQuadRule], const double (*rule_w)[kMaxQuadRule],
+                              const int *rule_n, LeafQuad3 &st, std::vector<double> &U, std::vector<double> &Wt,
+                              std::vector<double> &WC, std::vector<double> &LC, std::vector<double> &LN,
+                              std::vector<std::array<int, 3>> &counts, std::string &err);
+gwn_status leafquad3d_nodes(LeafQuad3 &st, const std::vector<int64_t> &qbase, int64_t total, void **out,
+                            std::string &err);
 // Clip the closed trim loops `in` of a patch's visible region to the half
 // x_dir <= c (low) or >= c of the unit square and map them to the half's
 // own unit square (trimclip.cpp).  false: the cut passes through a junction

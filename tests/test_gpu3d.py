@@ -265,16 +265,27 @@ def test_far_budget_repack_on_device(cfg3):
 
 
 def test_device_lbvh_matches_host():
-    """A model built for a device sorts its leaves and links the radix tree
-    there; the tree, the leaf order and the moments equal a host-only build
-    of the same patches exactly."""
+    """A model built for a device sorts its leaves, links the radix tree and
+    runs the leaf quadrature there (moments, multipole moments, node sets).
+    Against a host-only build of the same patches: the same tree and leaf
+    order, bit for bit; the same boxes; centres, moments and multipole
+    moments to rounding (the device sums the quadrature nodes in another
+    order)."""
     P = W.bodies(3, [("sphere", np.array([0.0, 0.0, 0.0]), 1.0), ("torus", np.array([2.5, 0.3, 0.1]), 0.8)])
-    P = W.Patches3D.from_list([(cp, w, W.square_trim()) for cp, w in P])
+    P = W.Patches3D.from_list([(cp, w, W.square_trim()) for cp, w in P]).concat(W.config4()[0].subset(range(0, 512, 7)))
     hd = G.gwn_build3d(P, presets.params(presets.FP64_3D))
     hh = G.gwn_build3d(P, presets.params(presets.FP64_3D, device=-1))
     try:
-        for what in (G.GWN_I_NODES, G.GWN_I_LEAVES, G.GWN_I_MULTIPOLE):
-            assert np.array_equal(G.gwn_inspect(hd, what), G.gwn_inspect(hh, what)), what
+        assert np.array_equal(G.gwn_inspect(hd, G.GWN_I_LEAVES), G.gwn_inspect(hh, G.GWN_I_LEAVES))
+        nd, nh = G.gwn_inspect(hd, G.GWN_I_NODES), G.gwn_inspect(hh, G.GWN_I_NODES)
+        assert np.array_equal(nd[:, :3], nh[:, :3]) and np.array_equal(nd[:, 7:], nh[:, 7:])
+        scale = np.abs(nh[:, 3:7]).max()
+        assert np.abs(nd[:, 3:7] - nh[:, 3:7]).max() <= 1e-13 * scale
+        for what in (G.GWN_I_MOMENTS, G.GWN_I_MULTIPOLE):
+            a, b = G.gwn_inspect(hd, what), G.gwn_inspect(hh, what)
+            assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max(), (what, np.abs(a - b).max(), np.abs(b).max())
+        fd, fh = G.gwn_inspect(hd, G.GWN_I_FARBETA), G.gwn_inspect(hh, G.GWN_I_FARBETA)
+        assert np.abs(fd - fh).max() <= 1e-6 * np.abs(fh).max()
     finally:
         G.gwn_free(hd)
         G.gwn_free(hh)
