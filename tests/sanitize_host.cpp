@@ -28,6 +28,22 @@ bool lbvh_device(int, int, int, const double *, const double *, const double *, 
     err = "no device in the host build";
     return false;
 }
+LeafQuad3::~LeafQuad3() {}
+gwn_status leafquad3d_moments(int, const std::vector<double> &, const std::vector<Trim3> &,
+                              const std::vector<int64_t> &, const std::vector<double> &,
+                              const double (*)[kMaxQuadRule], const double (*)[kMaxQuadRule], const int *,
+                              LeafQuad3 &, std::vector<double> &, std::vector<double> &, std::vector<double> &,
+                              std::vector<double> &, std::vector<double> &, std::vector<std::array<int, 3>> &,
+                              std::string &err)
+{
+    err = "no device in the host build";
+    return GWN_EUNSUPPORTED;
+}
+gwn_status leafquad3d_nodes(LeafQuad3 &, const std::vector<int64_t> &, int64_t, void **, std::string &err)
+{
+    err = "no device in the host build";
+    return GWN_EUNSUPPORTED;
+}
 }  // namespace gwn
 
 using namespace gwn;
