@@ -151,25 +151,41 @@ gwn_status build2d_host(const gwn_curves2d *c, const gwn_params *p, Model &m, st
 
     // AdaptiveSubdivision (Sec. 3.2): bisect while the AABB diagonal is not
     // below max_diag_frac of the model diagonal.  Depth is capped at 40.
-    const double limit = p->max_diag_frac * m.diag;
+    // The test compares the squared diagonal with the squared limit, in
+    // plain IEEE operations, as the device version does (moments2d.hip): a
+    // model built for a device subdivides there, to the same leaves.
+    const double limit = p->max_diag_frac * m.diag, limit2 = limit > 0 ? limit * limit : 0.0;
     std::vector<Cubic> leaves;
     leaves.reserve(work.size());
-    struct Item { Cubic c; int depth; };
-    std::vector<Item> st;
-    for (int64_t i = (int64_t)work.size() - 1; i >= 0; --i) st.push_back({work[i], 0});
-    while (!st.empty()) {
-        Item it = st.back();
-        st.pop_back();
-        double l[3], h[3];
-        aabb(it.c.h, l, h);
-        double dg = std::hypot(h[0] - l[0], h[1] - l[1]);
-        if (limit > 0 && dg >= limit && it.depth < 40) {
-            Cubic L = it.c, R = it.c;
-            split_half(it.c.h, L.h, R.h);
-            st.push_back({R, it.depth + 1});
-            st.push_back({L, it.depth + 1});
-        } else {
-            leaves.push_back(it.c);
+    if (p->device >= 0 && !work.empty()) {
+        std::vector<double> cubics(12 * work.size()), leaf_h;
+        std::vector<int32_t> leaf_curve;
+        for (size_t i = 0; i < work.size(); ++i) std::memcpy(&cubics[12 * i], work[i].h, sizeof work[i].h);
+        const gwn_status s = subdiv2d_device(p->device, cubics, limit2, leaf_h, leaf_curve, err);
+        if (s != GWN_OK) return s;
+        for (size_t l = 0; l < leaf_curve.size(); ++l) {
+            Cubic cu = work[leaf_curve[l]];
+            std::memcpy(cu.h, &leaf_h[12 * l], sizeof cu.h);
+            leaves.push_back(cu);
+        }
+    } else {
+        struct Item { Cubic c; int depth; };
+        std::vector<Item> st;
+        for (int64_t i = (int64_t)work.size() - 1; i >= 0; --i) st.push_back({work[i], 0});
+        while (!st.empty()) {
+            Item it = st.back();
+            st.pop_back();
+            double l[3], h[3];
+            aabb(it.c.h, l, h);
+            const double dx = h[0] - l[0], dy = h[1] - l[1];
+            if (limit2 > 0 && dx * dx + dy * dy >= limit2 && it.depth < 40) {
+                Cubic L = it.c, R = it.c;
+                split_half(it.c.h, L.h, R.h);
+                st.push_back({R, it.depth + 1});
+                st.push_back({L, it.depth + 1});
+            } else {
+                leaves.push_back(it.c);
+            }
         }
     }
     const int nl = (int)leaves.size();

@@ -267,6 +267,14 @@ double far_beta3d(const double *A, double r, int order, double tol);
 // tail2 as the host build lays them out, except tail2's rho entries, which
 // the caller fills.  chord_ends holds (ax, ay, bx, by) per leaf in DFS order;
 // end[i] is the end of node i's DFS subtree.
+// AdaptiveSubdivision of a 2D model on `device` (moments2d.hip): curve i is
+// the homogeneous cubic cubics[12 i .. 12 i + 11]; a piece is halved (de
+// Casteljau at t = 1/2) while the squared diagonal of its control-point box
+// is >= limit2 and its depth < 40.  Returns the leaves in the host build's
+// order (curve by curve, left to right in t): leaf_h (12 doubles each) and
+// the index of the curve each came from.
+gwn_status subdiv2d_device(int device, const std::vector<double> &cubics, double limit2,
+                           std::vector<double> &leaf_h, std::vector<int32_t> &leaf_curve, std::string &err);
 gwn_status moments2d_device(int device, const std::vector<HostNode> &nodes, const std::vector<int> &end,
                             const std::vector<double> &chord_ends, std::vector<double> &cmom2,
                             std::vector<double> &tail2, std::string &err);

@@ -1,4 +1,13 @@
-// Device computation of the per-cluster chord moments of a 2D model
+// Device preprocessing of a 2D model: the adaptive subdivision of the input
+// curves (Sec. 3.2) and the per-cluster chord moments.
+//
+// Subdivision: one thread per input curve walks its halving tree depth
+// first, left half first, with the same arithmetic as the host build (exact
+// midpoints, box by division, the squared diagonal against the squared
+// limit, no FMA contraction), so the leaves are the host's bit for bit; a
+// counting pass sizes each curve's leaves, a second pass writes them.
+//
+// Chord moments: the per-cluster chord moments of a 2D model
 // (ComputeUncenteredMoments of Alg. 1, taken directly about each cluster's
 // centroid): the centred complex moments m_k = integral (z - c)^k dz over the
 // chords of the cluster's leaves (Sec. 3.1, the series of Eq. taylor in
@@ -139,6 +148,120 @@ gwn_status moments2d_device(int device, const std::vector<HostNode> &nodes, cons
     if (e == hipSuccess) e = hipMemcpy(tail2.data(), d_tout.p, tbytes, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         err = std::string("device moments: ") + hipGetErrorString(e);
+        return GWN_EHIP;
+    }
+    return GWN_OK;
+}
+
+namespace {
+
+constexpr int kMaxSplitDepth = 40;
+
+// Leaves of curve i: counted (out_h == nullptr) into counts[i], or written
+// from offs[i] on (at most counts[i] of them: the counting pass bounds the
+// writes).
+__global__ __launch_bounds__(256) void k_subdiv2d(int64_t n, const double *__restrict__ cubics, double limit2,
+                                                int64_t *__restrict__ counts, const int64_t *__restrict__ offs,
+                                                double *__restrict__ out_h, int32_t *__restrict__ out_curve)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double stk[kMaxSplitDepth + 1][12];
+    int dep[kMaxSplitDepth + 1];
+    for (int k = 0; k < 12; ++k) stk[0][k] = cubics[12 * i + k];
+    dep[0] = 0;
+    int sp = 1;
+    int64_t pos = out_h ? offs[i] : 0, cnt = 0;
+    const int64_t end = out_h ? pos + counts[i] : 0;
+    while (sp > 0) {
+        --sp;
+        double c[12];
+        for (int k = 0; k < 12; ++k) c[k] = stk[sp][k];
+        const int depth = dep[sp];
+        double lo0 = INFINITY, lo1 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY;
+        for (int j = 0; j < 4; ++j) {
+            const double x = c[3 * j] / c[3 * j + 2], y = c[3 * j + 1] / c[3 * j + 2];
+            lo0 = fmin(lo0, x); hi0 = fmax(hi0, x);
+            lo1 = fmin(lo1, y); hi1 = fmax(hi1, y);
+        }
+        const double dx = hi0 - lo0, dy = hi1 - lo1;
+        if (limit2 > 0.0 && dx * dx + dy * dy >= limit2 && depth < kMaxSplitDepth) {
+            // halves at t = 1/2: right pushed first, so the left is taken next
+            double L[12], R[12];
+            for (int k = 0; k < 3; ++k) {
+                const double b0 = 0.5 * (c[k] + c[3 + k]), b1 = 0.5 * (c[3 + k] + c[6 + k]),
+                             b2 = 0.5 * (c[6 + k] + c[9 + k]);
+                const double c0 = 0.5 * (b0 + b1), c1 = 0.5 * (b1 + b2);
+                const double d0 = 0.5 * (c0 + c1);
+                L[k] = c[k]; L[3 + k] = b0; L[6 + k] = c0; L[9 + k] = d0;
+                R[k] = d0; R[3 + k] = c1; R[6 + k] = b2; R[9 + k] = c[9 + k];
+            }
+            for (int k = 0; k < 12; ++k) stk[sp][k] = R[k];
+            dep[sp] = depth + 1;
+            for (int k = 0; k < 12; ++k) stk[sp + 1][k] = L[k];
+            dep[sp + 1] = depth + 1;
+            sp += 2;
+        } else {
+            if (out_h && pos < end) {
+                for (int k = 0; k < 12; ++k) out_h[12 * pos + k] = c[k];
+                out_curve[pos] = (int32_t)i;
+                ++pos;
+            }
+            ++cnt;
+        }
+    }
+    if (!out_h) counts[i] = cnt;
+}
+
+}  // namespace
+
+gwn_status subdiv2d_device(int device, const std::vector<double> &cubics, double limit2,
+                           std::vector<double> &leaf_h, std::vector<int32_t> &leaf_curve, std::string &err)
+{
+    const int64_t n = (int64_t)(cubics.size() / 12);
+    leaf_h.clear();
+    leaf_curve.clear();
+    if (n == 0) return GWN_OK;
+    DevBuf d_c, d_cnt, d_off, d_h, d_i;
+    std::vector<int64_t> cnt(n), off(n);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc(&d_c.p, cubics.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_cnt.p, n * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMemcpy(d_c.p, cubics.data(), cubics.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_subdiv2d, grid, block, 0, 0, n, (const double *)d_c.p, limit2, (int64_t *)d_cnt.p,
+                           (const int64_t *)nullptr, (double *)nullptr, (int32_t *)nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(cnt.data(), d_cnt.p, n * sizeof(int64_t), hipMemcpyDeviceToHost);
+    int64_t total = 0;
+    if (e == hipSuccess)
+        for (int64_t i = 0; i < n; ++i) {
+            off[i] = total;
+            total += cnt[i];
+        }
+    if (e == hipSuccess && total > ((int64_t)1 << 30)) {
+        err = "too many leaves";
+        return GWN_EINVAL;
+    }
+    if (e == hipSuccess) e = hipMalloc(&d_off.p, n * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&d_h.p, (size_t)total * 12 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_i.p, (size_t)total * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(d_off.p, off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_subdiv2d, grid, block, 0, 0, n, (const double *)d_c.p, limit2, (int64_t *)d_cnt.p,
+                           (const int64_t *)d_off.p, (double *)d_h.p, (int32_t *)d_i.p);
+        e = hipGetLastError();
+    }
+    leaf_h.resize((size_t)total * 12);
+    leaf_curve.resize((size_t)total);
+    if (e == hipSuccess) e = hipMemcpy(leaf_h.data(), d_h.p, leaf_h.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(leaf_curve.data(), d_i.p, leaf_curve.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        err = std::string("device subdivision: ") + hipGetErrorString(e);
         return GWN_EHIP;
     }
     return GWN_OK;

@@ -28,6 +28,12 @@ bool lbvh_device(int, int, int, const double *, const double *, const double *, 
     err = "no device in the host build";
     return false;
 }
+gwn_status subdiv2d_device(int, const std::vector<double> &, double, std::vector<double> &, std::vector<int32_t> &,
+                           std::string &err)
+{
+    err = "no device in the host build";
+    return GWN_EUNSUPPORTED;
+}
 LeafQuad3::~LeafQuad3() {}
 gwn_status leafquad3d_moments(int, const std::vector<double> &, const std::vector<Trim3> &,
                               const std::vector<int64_t> &, const std::vector<double> &,

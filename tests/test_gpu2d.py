@@ -349,6 +349,25 @@ def _duplicates():
     return W.Curves2D.from_list(W.circle_curves((0, 0), 1.0) + [seg] * 200)
 
 
+@pytest.mark.parametrize("frac", [0.1, 0.01, 0.002])
+def test_device_subdivision_matches_host(frac):
+    """A model built for a device runs the adaptive subdivision there (one
+    thread per curve, the host's arithmetic): the same leaves, in the same
+    order, bit for bit, from the paper's threshold down to thousands of
+    pieces per loop."""
+    curves = W.config2(grid=4)[0].concat(W.star_loop(seed=7, n_curves=64))
+    hd = G.gwn_build2d(curves, presets.params(presets.FP64_2D, max_diag_frac=frac))
+    hh = G.gwn_build2d(curves, presets.params(presets.FP64_2D, max_diag_frac=frac, device=-1))
+    try:
+        ld, lh = G.gwn_inspect(hd, G.GWN_I_LEAVES), G.gwn_inspect(hh, G.GWN_I_LEAVES)
+        print(f"subdivision {frac}: {curves.n} curves -> {lh.shape[0]} leaves", flush=True)
+        assert lh.shape[0] >= curves.n and np.array_equal(ld, lh)
+        assert np.array_equal(G.gwn_inspect(hd, G.GWN_I_NODES), G.gwn_inspect(hh, G.GWN_I_NODES))
+    finally:
+        G.gwn_free(hd)
+        G.gwn_free(hh)
+
+
 @pytest.mark.parametrize("which", ["star", "drawing", "duplicates"])
 def test_device_moments_match_host(which):
     """A model built for a device computes its cluster moments and
