@@ -55,8 +55,8 @@ constexpr int kRadialN = 6;
 constexpr int kGKo = 2 * kOuterN + 1;      // Kronrod nodes per outer panel
 constexpr int kGKr = 2 * kRadialN + 1;     // Kronrod nodes per radial piece
 constexpr int kMaxPanelsSide = 40;
-constexpr int kOuterLevels = 5;    // an outer panel is refined into at most 32
-constexpr int kRadialLevels = 5;   // a radial piece into at most 32
+constexpr int kOuterLevels = 7;    // an outer panel is refined into at most 128
+constexpr int kRadialLevels = 7;   // a radial piece into at most 128
 
 // Gauss-Kronrod nodes and weights on [0, 1] of the outer and radial pairs
 // (increasing; the odd ones are the Gauss nodes, g* their Gauss weights).
@@ -88,9 +88,11 @@ GWN_HD inline double gk_error(double K, double G, double resasc)
 GWN_HD inline double gk_round(double resabs) { return 50.0 * 2.220446049250313e-16 * resabs; }
 
 // A (query, leaf) pair stops refining after this many integrand
-// evaluations (about 20 times a typical pair); running out is a budget
-// overrun.
-constexpr long long kMaxEvalsPerPair = 100000;
+// evaluations (a few hundred times a typical pair: only the hardest pairs,
+// queries within a hair of a trim edge or a fold, come near it, one wave
+// each, so a deep budget costs the launch nothing measurable); running out
+// is a budget overrun.
+constexpr long long kMaxEvalsPerPair = 1600000;
 
 // Error budget of one leaf, spent panel by panel: a panel may use the
 // remaining budget divided by the panels still to come, so the sum of the
