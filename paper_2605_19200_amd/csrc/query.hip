@@ -147,24 +147,46 @@ __device__ __forceinline__ double chord_angle(double ax, double ay, double bx, d
     return fast_atan2(cr, dt);
 }
 
-// Sum of the chord angles seen from q (direct leaf contributions).
-// (Measured on gfx950: one FP64 atan2 per chord is cheaper than carrying a
-// rescaled complex product of the chords and recovering the 2 pi multiple
-// from a coarse FP32 sum.)
+// Sum of the chord angles seen from q (direct leaf contributions), without
+// an arctangent per chord: the chord a -> b subtends arg(z), z = dot(a, b) +
+// i cross(a, b), so the sum is the argument of the product of the z's plus
+// 2 pi for every time the running argument passes +-pi.  Both arguments lie
+// in (-pi, pi], so a pass past +pi can only happen when both are in [0, pi]
+// and the product falls below the real axis, and past -pi only when both
+// are negative and the product rises to or above it.  z and the product are
+// rescaled by powers of two (exact), and one arctangent at the end gives
+// the argument.  One complex multiply and a few sign tests per chord are
+// cheaper than an FP64 arctangent.
 struct AngleAcc {
-    double sum;
+    double pr, pi;      // product of the chords' (dot, cross), rescaled by powers of 2
+    int turns;          // times the product's argument wrapped past +-pi
     double extra;       // terminal-piece angles
 };
 
-__device__ __forceinline__ void angle_init(AngleAcc &A) { A.sum = 0.0; A.extra = 0.0; }
+__device__ __forceinline__ void angle_init(AngleAcc &A) { A.pr = 1.0; A.pi = 0.0; A.turns = 0; A.extra = 0.0; }
 
 __device__ __forceinline__ void angle_add_chord(AngleAcc &A, double cr, double dt)
 {
     if (cr == 0.0 && dt <= 0.0) return;   // q on the chord or at an end point
-    A.sum += fast_atan2(cr, dt);
+    // z = dt + i cr has the chord's angle as argument; scale it exactly
+    int ez;
+    (void)frexp(fmax(fabs(dt), fabs(cr)), &ez);
+    const double zr = ldexp(dt, -ez), zi = ldexp(cr, -ez);
+    const double nr = A.pr * zr - A.pi * zi, ni = A.pr * zi + A.pi * zr;
+    // both arguments in [0, pi] and the product below the real axis: the sum
+    // passed pi; both in (-pi, 0) and the product at or above: passed -pi
+    if (A.pi >= 0.0 && zi >= 0.0 && ni < 0.0) ++A.turns;
+    else if (A.pi < 0.0 && zi < 0.0 && (ni > 0.0 || (ni == 0.0 && nr < 0.0))) --A.turns;
+    int ep;
+    (void)frexp(fmax(fabs(nr), fabs(ni)), &ep);
+    A.pr = ldexp(nr, -ep);
+    A.pi = ldexp(ni, -ep) + 0.0;   // no -0: its atan2 would be -pi where the count takes +pi
 }
 
-__device__ __forceinline__ double angle_total(const AngleAcc &A) { return A.sum + A.extra; }
+__device__ __forceinline__ double angle_total(const AngleAcc &A)
+{
+    return 6.283185307179586 * A.turns + fast_atan2(A.pi, A.pr) + A.extra;
+}
 
 __device__ __forceinline__ double lerp_exact(double a, double b, double t, double s)
 {
