@@ -163,16 +163,46 @@ GWN_HD inline void hom_eval(const double *__restrict__ h, double u, double v, do
     e.Av[0] = fma(-qx, Hv[3], Hv[0]); e.Av[1] = fma(-qy, Hv[3], Hv[1]); e.Av[2] = fma(-qz, Hv[3], Hv[2]);
 }
 
-// solid angle density det[A, A_u, A_v] / |A|^3
-GWN_HD inline double density(const HomEval &e)
+// 1 / sqrt(x) and 1 / x for normal x > 0: on the device the hardware
+// estimates refined by two Newton steps (within an ulp or two, no IEEE
+// square root or division sequence); on the host the plain operations.
+GWN_HD inline double inv_sqrt(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+
+GWN_HD inline double inv_fast(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
+
+// solid angle density det[A, A_u, A_v] / |A|^3, and 1 / |A| in *rs (0 when
+// A = 0, where the density is 0)
+GWN_HD inline double density(const HomEval &e, double *rs)
 {
     const double cx = e.Au[1] * e.Av[2] - e.Au[2] * e.Av[1];
     const double cy = e.Au[2] * e.Av[0] - e.Au[0] * e.Av[2];
     const double cz = e.Au[0] * e.Av[1] - e.Au[1] * e.Av[0];
     const double det = e.A[0] * cx + e.A[1] * cy + e.A[2] * cz;
     const double r2 = e.A[0] * e.A[0] + e.A[1] * e.A[1] + e.A[2] * e.A[2];
+    *rs = 0.0;
     if (r2 == 0.0) return 0.0;
-    return det / (r2 * sqrt(r2));
+    const double ir = inv_sqrt(r2);
+    *rs = ir;
+    return det * (ir * ir * ir);
 }
 
 // Euclidean offset S - q and partials from the homogeneous evaluation
@@ -481,15 +511,15 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
                     jac = 1.0;
                 } else {
                     // sinh and cosh from one expm1: e - 1/e = em (1 + 1/e)
-                    const double em = expm1(tmu * x), ie = 1.0 / (1.0 + em);
+                    const double em = expm1(tmu * x), ie = inv_fast(1.0 + em);
                     tau = teps * 0.5 * (em + em * ie);
                     jac = teps * tmu * 0.5 * (1.0 + em + ie);
                 }
                 HomEval ev;
                 hom_eval(h, fr.cu + tau * tru, fr.cv + tau * trv, qx, qy, qz, ev);
-                fx = jac * tau * density(ev);
-                const double a2 = ev.A[0] * ev.A[0] + ev.A[1] * ev.A[1] + ev.A[2] * ev.A[2];
-                nz = fabs(fx) * (1.0 + (a2 > 0.0 ? qnorm * fabs(ev.W) / sqrt(a2) : 0.0));
+                double rs;
+                fx = jac * tau * density(ev, &rs);
+                nz = fabs(fx) * (1.0 + qnorm * fabs(ev.W) * rs);
             }
             const double wk = node ? wr_i : 0.0;
             const double wg = node ? gr_i : 0.0;

@@ -100,7 +100,7 @@ __device__ double leaf3d(const TravParams &M, const Node3 *__restrict__ nd, int 
         for (int k = 0; k < cnt; ++k) {
             const double rx = qn[k].x[0] - qx, ry = qn[k].x[1] - qy, rz = qn[k].x[2] - qz;
             const double rr = rx * rx + ry * ry + rz * rz;
-            const double inv = 1.0 / sqrt(rr);
+            const double inv = inv_sqrt(rr);
             om += (qn[k].n[0] * rx + qn[k].n[1] * ry + qn[k].n[2] * rz) * (inv * inv * inv);
         }
         if (COUNT) { ctr.v[GWN_C_LEAF_FAST]++; ctr.v[GWN_C_ANGLES] += cnt; }
@@ -122,8 +122,15 @@ __device__ __forceinline__ T multipole3d(T sx, T sy, T sz, const T *__restrict__
 {
     const T ir = mp[0];
     const T x = sx * ir, y = sy * ir, z = sz * ir;
-    const T inv2 = T(1) / (x * x + y * y + z * z);
-    T mmr = sqrt(inv2), mmi = T(0);
+    T inv2, mmr;
+    if constexpr (sizeof(T) == 8) {
+        mmr = inv_sqrt(x * x + y * y + z * z);   // 1 / rho
+        inv2 = mmr * mmr;
+    } else {
+        inv2 = T(1) / (x * x + y * y + z * z);
+        mmr = sqrt(inv2);
+    }
+    T mmi = T(0);
     T omega = T(0);
     for (int m = 0; m <= L; ++m) {
         if (m > 0) {
@@ -164,8 +171,15 @@ __device__ __forceinline__ T multipole3d_fixed(T sx, T sy, T sz, const T *__rest
 {
     const T ir = mp[0];
     const T x = sx * ir, y = sy * ir, z = sz * ir;
-    const T inv2 = T(1) / (x * x + y * y + z * z);
-    T mmr = sqrt(inv2), mmi = T(0);
+    T inv2, mmr;
+    if constexpr (sizeof(T) == 8) {
+        mmr = inv_sqrt(x * x + y * y + z * z);   // 1 / rho
+        inv2 = mmr * mmr;
+    } else {
+        inv2 = T(1) / (x * x + y * y + z * z);
+        mmr = sqrt(inv2);
+    }
+    T mmi = T(0);
     T omega = T(0);
 #pragma unroll
     for (int m = 0; m <= L; ++m) {
