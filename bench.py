@@ -47,6 +47,16 @@ def algorithmic_flops(c: dict, order: int) -> float:
 #   radial map (x, expm1, 1/(1+e), tau, Jacobian, u, v)                 17
 #   f = Jacobian tau density, rounding weight, Kronrod sums             20
 NEAR_FLOPS_PER_NODE = 475
+# Algorithmic FP64 operations of the 3D traversal (k_trav3d), per event:
+#   node test: q - c (3), |q - c|^2 (5), against beta^2 r^2 (1)            9
+#   node-set node: x - q (3), |r|^2 (5), 1/|r| (1), n . r (5), / |r|^3 (2),
+#     accumulate (2)                                                      18
+#   far term of order 6 (degrees 1..7 of the solid harmonics): scaling and
+#     1/rho (9), 7 diagonal steps (8 each), 28 column steps (9 each),
+#     35 moment contractions (4 each)                                    461
+TRAV_FLOPS_PER_NODE_TEST = 9
+TRAV_FLOPS_PER_SET_NODE = 18
+TRAV_FLOPS_PER_FAR_TERM = 461
 
 
 def physical_cores():
@@ -194,6 +204,14 @@ def bench3d() -> dict:
                 "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_near3d<false, false>",
                 "kernel_ms": near, "integrand_nodes": int(c["pieces"]), "flops_per_node": NEAR_FLOPS_PER_NODE,
                 "flops_per_launch": float(flops)}
+            tflops = (c["nodes"] * TRAV_FLOPS_PER_NODE_TEST + c["angles"] * TRAV_FLOPS_PER_SET_NODE
+                      + c["far"] * TRAV_FLOPS_PER_FAR_TERM)
+            tt = tflops / (trav / 1e3) / 1e12
+            out["roofline_k_trav3d"] = {
+                "bound": "alu", "achieved": tt, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tt / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_trav3d<false, false>",
+                "kernel_ms": trav, "node_tests": int(c["nodes"]), "node_set_nodes": int(c["angles"]),
+                "far_terms": int(c["far"]), "flops_per_launch": float(tflops)}
         m.close()
         print(f"[bench] 3D bodies {name}: {dt * 1e3:.1f} ms per grid (traversal {trav:.1f} ms, near field "
               f"{near:.1f} ms)", file=sys.stderr, flush=True)
