@@ -95,14 +95,23 @@ MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125
 #   far_tol 1e-8: 105.2 ms, 3.4e-8     |  1015 ms, 8.4e-8
 #   far_tol 2e-8:  99.7 ms, 6.4e-8     |  1010 ms, 8.3e-8  (chosen)
 #   far_tol 3e-8:  96.4 ms, 8.5e-8     |   993 ms, 1.2e-7
+# The near-field rule takes a leaf closer than near_ratio x its box
+# diagonal; farther leaves use the precomputed node sets.  Against every
+# query of a launch at near_ratio 0.5 (where 0.35 and 0.5 give the same
+# values), max |dw| on the CAD assembly / bodies scene:
+#   near_ratio 0.25 (library default): 1.1e-6 / 2.5e-7, 939 / 92 ms
+#              0.28:                   2.6e-7 / 1.2e-8, 999 / 98 ms  (chosen)
+#              0.30:                   1.1e-7 / 1.2e-8
+#              0.20:                   9.2e-6 (against 0.25) -- too close
 FP64_3D = dict(beta=5.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, far_tol=2e-8, wave_accept=1,
-               precision=G.GWN_FP64)
+               near_ratio=0.28, precision=G.GWN_FP64)
 # A reached leaf that passes the far test itself takes its own expansion
 # (leaf_far, the default): on the checked sets this halves the node-set work
 # per query (CAD assembly: 113k -> 53k integrand nodes) at the same error.
 # The paper's setting evaluates every reached leaf directly (Alg. 1).
 PAPER_ORDER_3D = dict(beta=16.0, taylor_order=2, leaf_far=0, eps_q=1e-8, precision=G.GWN_FP64)
 MIXED_3D = dict(beta=5.0, beta_mixed=3.0, taylor_order=6, max_diag_frac=0.0125, eps_q=1e-8, far_tol=1e-8,
+                near_ratio=0.28,
                 precision=G.GWN_MIXED,
                 reclass_band=1e-2)
 

@@ -96,6 +96,28 @@ def test_cad_assembly_full_launch(cad, form):
     m.close()
 
 
+def test_cad_assembly_every_query_against_wider_near_field(cad):
+    """Every query of the full CAD launch, not only the fixture rows: the
+    FP64 preset against the same model with the near-field rule taking
+    every leaf within half its box diagonal (the node-set rules then serve
+    only well-separated leaves; 0.35 and 0.5 give the same values).  The
+    preset's near_ratio keeps the node-set error of every query within the
+    1e-6 bound with a margin."""
+    P, q, rows, ref = cad
+    m = G.Model(P, presets.params(presets.FP64_3D))
+    w, _ = run(m, q)
+    flagged_rows_reported("cad assembly preset", m, w, q)
+    m.set(near_ratio=0.5)
+    w5, _ = run(m, q)
+    flagged_rows_reported("cad assembly near_ratio 0.5", m, w5, q)
+    ok = np.isfinite(w) & np.isfinite(w5)
+    d = np.abs(w[ok] - w5[ok])
+    print(f"cad assembly: preset vs near_ratio 0.5 over {ok.sum()} queries: max {d.max():.3e}, "
+          f"{int((d > 1e-7).sum())} above 1e-7", flush=True)
+    assert ok.sum() >= (1 - MAX_FLAGGED) * q.shape[0] and d.max() <= 5e-7
+    m.close()
+
+
 @pytest.fixture(scope="module")
 def bodies():
     rows, qf, wf, hdr = F.load(os.path.join(HERE, "golden", "oracle_bodies_scene.txt"))
