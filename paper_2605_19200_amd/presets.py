@@ -97,8 +97,8 @@ MIXED_2D = dict(beta=3.25, beta_mixed=2.0, taylor_order=12, max_diag_frac=0.0125
 #   far_tol 3e-8:  96.4 ms, 8.5e-8     |   993 ms, 1.2e-7
 # The near-field rule takes a leaf closer than near_ratio x its box
 # diagonal; farther leaves use the precomputed node sets.  Against every
-# query of a launch at near_ratio 0.5 (where 0.35 and 0.5 give the same
-# values), max |dw| on the CAD assembly / bodies scene:
+# query of a launch at near_ratio 0.5 (0.35 gives the same maximum and
+# counts), max |dw| on the CAD assembly / bodies scene:
 #   near_ratio 0.25 (library default): 1.1e-6 / 2.5e-7, 939 / 92 ms
 #              0.28:                   2.6e-7 / 1.2e-8, 999 / 98 ms  (chosen)
 #              0.30:                   1.1e-7 / 1.2e-8

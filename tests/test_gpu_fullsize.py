@@ -100,7 +100,7 @@ def test_cad_assembly_every_query_against_wider_near_field(cad):
     """Every query of the full CAD launch, not only the fixture rows: the
     FP64 preset against the same model with the near-field rule taking
     every leaf within half its box diagonal (the node-set rules then serve
-    only well-separated leaves; 0.35 and 0.5 give the same values).  The
+    only well-separated leaves; 0.35 and 0.5 differ from the preset alike).  The
     preset's near_ratio keeps the node-set error of every query within the
     1e-6 bound with a margin."""
     P, q, rows, ref = cad
