@@ -730,6 +730,9 @@ double far_beta3d(const double *A, double r, int order, double tol)
 void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims)
 {
     const auto &T = m.tree.nodes;
+    // end of each node's DFS subtree (a leaf's is the next index)
+    std::vector<int32_t> end(T.size());
+    for (size_t i = T.size(); i-- > 0;) end[i] = T[i].is_leaf ? (int32_t)i + 1 : end[T[i].right];
     nodes.assign(T.size(), Node3{});
     for (size_t i = 0; i < T.size(); ++i) {
         const HostNode &h = T[i];
@@ -787,6 +790,7 @@ void pack3d(const Model &m, std::vector<Node3> &nodes, std::vector<Prim3> &prims
         for (int a = 0; a < 3; ++a) n.fc[a] = (float)n.c[a];
         n.fr2 = (float)n.r2;
         n.r2 = far_r2;
+        n.escape = end[i];
         for (int k = 0; k < 22; ++k) n.ft[k] = (float)n.t[k];
     }
     prims.assign(m.leaf_src.size(), Prim3{});

@@ -111,6 +111,10 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> 
     const auto &T = m.tree.nodes;
     nodes.assign(T.size(), Node2{});
     hot.assign(T.size(), Hot2{});
+    // end of each node's DFS subtree: a leaf's is the next index, an
+    // internal node's its right child's
+    std::vector<int32_t> end(T.size());
+    for (size_t i = T.size(); i-- > 0;) end[i] = T[i].is_leaf ? (int32_t)i + 1 : end[T[i].right];
     for (size_t i = 0; i < T.size(); ++i) {
         const HostNode &h = T[i];
         Node2 &n = nodes[i];
@@ -164,6 +168,7 @@ static void pack2d(const Model &m, std::vector<Node2> &nodes, std::vector<Hot2> 
         }
         t.right = n.right;
         t.degree = n.degree;
+        t.escape = end[i];
     }
     prims.assign(m.leaf_src.size(), Prim2{});
     for (size_t l = 0; l < prims.size(); ++l)

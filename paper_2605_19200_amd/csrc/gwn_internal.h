@@ -76,7 +76,8 @@ struct alignas(64) Hot2 {
     int32_t right;
     int32_t degree;
     float f[4];
-    float pad[2];
+    int32_t escape;   // first node after this node's subtree in DFS order
+    float pad;
 };
 static_assert(sizeof(Hot2) == 64, "Hot2 must be 64 bytes");
 
@@ -108,7 +109,8 @@ struct alignas(128) Node3 {
     float fc[3];
     float fr2;
     float ft[22];
-    float pad[6];
+    int32_t escape;   // first node after this node's subtree in DFS order
+    float pad[5];
 };
 static_assert(sizeof(Node3) == 384, "Node3 layout");
 

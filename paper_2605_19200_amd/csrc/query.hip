@@ -362,12 +362,65 @@ __device__ __forceinline__ T taylor2d_fixed(T dx, T dy, T d2, T r, const T *__re
     return -(a0 + a1);
 }
 
+// FP64 traversal with wave acceptance: a cluster is far only when every
+// lane of `mask` passes its test, so the wave accepts or descends as a
+// whole and its lane mask never changes.  The depth-first walk then needs no
+// stack: after a leaf or an accepted cluster it continues at the node's
+// escape index (the first node after its subtree), after a rejected cluster
+// at its left child (the next index).  Same nodes in the same order as the
+// stack walk, so the same sums bit for bit.
+template <bool COUNT>
+__device__ double traverse2d_wave(const DevModel &M, double qx, double qy, uint64_t mask, Ctr &ctr, bool &overflow)
+{
+    const Node2 *__restrict__ nodes = (const Node2 *)M.nodes;
+    const Hot2 *__restrict__ hot = (const Hot2 *)M.hot;
+    const Prim2 *__restrict__ prims = (const Prim2 *)M.prims;
+    const bool me = (mask >> lane_id()) & 1;
+    const float qxf = (float)qx, qyf = (float)qy;
+    const double beta2 = M.beta2;
+    const int order = M.order;
+    const double eps_on = M.eps_on;
+    const int n_nodes = M.n_nodes;
+    double acc = 0.0;
+    AngleAcc A;
+    angle_init(A);
+    int cur = 0;
+    while (cur < n_nodes) {
+        const Hot2 *hd = hot + cur;
+        const int right = hd->right;
+        const double bb[4] = {hd->a[0], hd->a[1], hd->a[2], hd->a[3]};
+        const float ff[4] = {hd->f[0], hd->f[1], hd->f[2], hd->f[3]};
+        if (right < 0) {
+            if (me) leaf2d<COUNT>(hd, bb, ff, prims, qx, qy, qxf, qyf, eps_on, A, ctr, overflow);
+            cur = cur + 1;
+            continue;
+        }
+        if (COUNT && me) ctr.v[GWN_C_NODES]++;
+        const double dx = qx - bb[0], dy = qy - bb[1];
+        const double d2 = dx * dx + dy * dy;
+        if (__ballot(me && d2 > beta2 * bb[2]) == mask) {
+            if (me) {
+                acc += order == kMaxOrder2D ? taylor2d_fixed<double, kMaxOrder2D>(dx, dy, d2, bb[3], nodes[cur].m)
+                       : order == kMixedOrder2D + 1
+                           ? taylor2d_fixed<double, kMixedOrder2D + 1>(dx, dy, d2, bb[3], nodes[cur].m)
+                           : taylor2d<double>(dx, dy, d2, bb[3], nodes[cur].m, order);
+                if (COUNT) ctr.v[GWN_C_FAR]++;
+            }
+            cur = uniform_i(hd->escape);
+        } else {
+            cur = cur + 1;
+        }
+    }
+    return (angle_total(A) + acc) * (1.0 / (2.0 * kPi));
+}
+
 // Traversal of one wave over a 2D model.  `mask`: lanes taking part (wave
 // uniform).  F32: far-field tests and Taylor terms in FP32 (mixed form).
 template <bool F32, bool COUNT>
 __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t mask, StackLDS &S, int w,
                              Ctr &ctr, bool &overflow)
 {
+    if (!F32 && M.wave_accept) return traverse2d_wave<COUNT>(M, qx, qy, mask, ctr, overflow);
     const Node2 *__restrict__ nodes = (const Node2 *)M.nodes;
     const Hot2 *__restrict__ hot = (const Hot2 *)M.hot;
     const Prim2 *__restrict__ prims = (const Prim2 *)M.prims;

@@ -244,6 +244,44 @@ __device__ __forceinline__ bool far_term3d(const TravParams &M, const Node3 *__r
     return far;
 }
 
+// FP64 traversal with wave acceptance: every test is decided for the whole
+// wave, so its lane mask never changes and the depth-first walk needs no
+// stack (after a leaf or an accepted cluster: the node's escape index; after
+// a rejected cluster: the next index).  The same nodes in the same order as
+// the stack walk, the same sums bit for bit.
+template <bool COUNT>
+__device__ double traverse3d_wave(const DevModel &Mdl, double qx, double qy, double qz, uint64_t mask, int &ncnt,
+                                  int32_t *__restrict__ mylist, Ctr &ctr)
+{
+    const Node3 *__restrict__ nodes = (const Node3 *)Mdl.nodes;
+    const TravParams M = trav_params(Mdl);
+    const bool me = (mask >> lane_id()) & 1;
+    const int n_nodes = Mdl.n_nodes;
+    double acc_far = 0.0, acc_leaf = 0.0;
+    int cur = 0;
+    while (cur < n_nodes) {
+        const Node3 *nd = nodes + cur;
+        const int right = nd->right;
+        bool far = false;
+        if (right < 0) {
+            if (me && M.leaf_far) {
+                far = far_term3d<false>(M, nd, cur, qx, qy, qz, acc_far, mask);
+                if (COUNT && far) { ctr.v[GWN_C_FAR]++; ctr.v[GWN_C_LEAVES]++; }
+            }
+            acc_leaf += leaf3d<COUNT>(M, nd, cur, qx, qy, qz, me && !far, ncnt, mylist, ctr);
+            cur = cur + 1;
+            continue;
+        }
+        if (me) {
+            if (COUNT) ctr.v[GWN_C_NODES]++;
+            far = far_term3d<false>(M, nd, cur, qx, qy, qz, acc_far, mask);
+            if (COUNT && far) ctr.v[GWN_C_FAR]++;
+        }
+        cur = __ballot(me && far) ? uniform_i(nd->escape) : cur + 1;
+    }
+    return acc_far + acc_leaf;
+}
+
 // Traversal of one wave (Alg. 1 query loop) over a 3D model.  With
 // leaf_far, a reached leaf that passes the far test itself takes its own
 // far-field expansion, like a cluster; the rest of the reached leaves are
@@ -252,6 +290,7 @@ template <bool F32, bool COUNT>
 __device__ double traverse3d(const DevModel &Mdl, double qx, double qy, double qz, uint64_t mask, StackLDS &S,
                              int w, int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
+    if (!F32 && Mdl.wave_accept) return traverse3d_wave<COUNT>(Mdl, qx, qy, qz, mask, ncnt, mylist, ctr);
     const Node3 *__restrict__ nodes = (const Node3 *)Mdl.nodes;
     const TravParams M = trav_params(Mdl);
     const int lane = lane_id();
