@@ -211,10 +211,9 @@ typedef struct {
                               subset, a split, another order of points
                               that share a sort key, or another call size,
                               which sets the queries per wave) may differ
-                              within the error budget.  Applies to the FP64
-                              tests (also the mixed form's FP64
-                              re-evaluation); the FP32 pass keeps per-query
-                              tests.                                       */
+                              within the error budget.  Applies to every
+                              far test: the FP64 form and both passes of
+                              the mixed form.                              */
     double far_tol;        /* Q: error budget of the FP64 far test, per
                               accepted cluster.  0 (default): a cluster is
                               far when ||q - c|| > beta * r.  > 0: each

@@ -362,14 +362,14 @@ __device__ __forceinline__ T taylor2d_fixed(T dx, T dy, T d2, T r, const T *__re
     return -(a0 + a1);
 }
 
-// FP64 traversal with wave acceptance: a cluster is far only when every
-// lane of `mask` passes its test, so the wave accepts or descends as a
+// Traversal with wave acceptance (FP64, or the FP32 pass of the mixed
+// form): a cluster is far only when every lane of `mask` passes its test, so the wave accepts or descends as a
 // whole and its lane mask never changes.  The depth-first walk then needs no
 // stack: after a leaf or an accepted cluster it continues at the node's
 // escape index (the first node after its subtree), after a rejected cluster
 // at its left child (the next index).  Same nodes in the same order as the
 // stack walk, so the same sums bit for bit.
-template <bool COUNT>
+template <bool F32, bool COUNT>
 __device__ double traverse2d_wave(const DevModel &M, double qx, double qy, uint64_t mask, Ctr &ctr, bool &overflow)
 {
     const Node2 *__restrict__ nodes = (const Node2 *)M.nodes;
@@ -378,6 +378,7 @@ __device__ double traverse2d_wave(const DevModel &M, double qx, double qy, uint6
     const bool me = (mask >> lane_id()) & 1;
     const float qxf = (float)qx, qyf = (float)qy;
     const double beta2 = M.beta2;
+    const float beta2f = (float)M.beta2_mixed;
     const int order = M.order;
     const double eps_on = M.eps_on;
     const int n_nodes = M.n_nodes;
@@ -396,6 +397,24 @@ __device__ double traverse2d_wave(const DevModel &M, double qx, double qy, uint6
             continue;
         }
         if (COUNT && me) ctr.v[GWN_C_NODES]++;
+        if (F32) {
+            const float dx = qxf - ff[0], dy = qyf - ff[1];
+            const float d2 = dx * dx + dy * dy;
+            if (__ballot(me && d2 > beta2f * ff[2]) == mask) {
+                if (me) {
+                    acc += order >= kMaxOrder2D - 1
+                               ? (double)taylor2d_fixed<float, kMaxOrder2D - 1>(dx, dy, d2, ff[3], nodes[cur].fm)
+                           : order >= kMixedOrder2D
+                               ? (double)taylor2d_fixed<float, kMixedOrder2D>(dx, dy, d2, ff[3], nodes[cur].fm)
+                               : (double)taylor2d<float>(dx, dy, d2, ff[3], nodes[cur].fm, order);
+                    if (COUNT) ctr.v[GWN_C_FAR]++;
+                }
+                cur = uniform_i(hd->escape);
+            } else {
+                cur = cur + 1;
+            }
+            continue;
+        }
         const double dx = qx - bb[0], dy = qy - bb[1];
         const double d2 = dx * dx + dy * dy;
         if (__ballot(me && d2 > beta2 * bb[2]) == mask) {
@@ -420,7 +439,7 @@ template <bool F32, bool COUNT>
 __device__ double traverse2d(const DevModel &M, double qx, double qy, uint64_t mask, StackLDS &S, int w,
                              Ctr &ctr, bool &overflow)
 {
-    if (!F32 && M.wave_accept) return traverse2d_wave<COUNT>(M, qx, qy, mask, ctr, overflow);
+    if (M.wave_accept) return traverse2d_wave<F32, COUNT>(M, qx, qy, mask, ctr, overflow);
     const Node2 *__restrict__ nodes = (const Node2 *)M.nodes;
     const Hot2 *__restrict__ hot = (const Hot2 *)M.hot;
     const Prim2 *__restrict__ prims = (const Prim2 *)M.prims;

@@ -214,8 +214,8 @@ __device__ __forceinline__ T multipole3d_fixed(T sx, T sy, T sz, const T *__rest
 }
 
 // Far test of node `cur` for one lane, adding its far-field term when the
-// test passes; true when it does.  With wave acceptance the FP64 test passes
-// only when it passes for every lane of `curmask` (the lanes at this node).
+// test passes; true when it does.  With wave acceptance the test passes only
+// when it passes for every lane of `curmask` (the lanes at this node).
 template <bool F32>
 __device__ __forceinline__ bool far_term3d(const TravParams &M, const Node3 *__restrict__ nd, int cur, double qx,
                                            double qy, double qz, double &acc_far, uint64_t curmask)
@@ -223,7 +223,8 @@ __device__ __forceinline__ bool far_term3d(const TravParams &M, const Node3 *__r
     if (F32) {
         const float sx = nd->fc[0] - (float)qx, sy = nd->fc[1] - (float)qy, sz = nd->fc[2] - (float)qz;
         const float r2 = sx * sx + sy * sy + sz * sz;
-        const bool far = r2 > M.beta2_mixed * nd->fr2;
+        bool far = r2 > M.beta2_mixed * nd->fr2;
+        if (M.wave_accept && __ballot(far) != curmask) far = false;
         if (far) {
             const float *mp = (const float *)M.fmpole + (size_t)cur * kMpoleStride;
             acc_far += M.order + 1 == kMaxL3 ? (double)multipole3d_fixed<float, kMaxL3>(-sx, -sy, -sz, mp)
@@ -244,12 +245,13 @@ __device__ __forceinline__ bool far_term3d(const TravParams &M, const Node3 *__r
     return far;
 }
 
-// FP64 traversal with wave acceptance: every test is decided for the whole
-// wave, so its lane mask never changes and the depth-first walk needs no
-// stack (after a leaf or an accepted cluster: the node's escape index; after
-// a rejected cluster: the next index).  The same nodes in the same order as
+// Traversal with wave acceptance (FP64, or the FP32 pass of the mixed
+// form): every test is decided for the whole wave, so its lane mask never
+// changes and the depth-first walk needs no stack (after a leaf or an
+// accepted cluster: the node's escape index; after a rejected cluster: the
+// next index).  The same nodes in the same order as
 // the stack walk, the same sums bit for bit.
-template <bool COUNT>
+template <bool F32, bool COUNT>
 __device__ double traverse3d_wave(const DevModel &Mdl, double qx, double qy, double qz, uint64_t mask, int &ncnt,
                                   int32_t *__restrict__ mylist, Ctr &ctr)
 {
@@ -265,7 +267,7 @@ __device__ double traverse3d_wave(const DevModel &Mdl, double qx, double qy, dou
         bool far = false;
         if (right < 0) {
             if (me && M.leaf_far) {
-                far = far_term3d<false>(M, nd, cur, qx, qy, qz, acc_far, mask);
+                far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far, mask);
                 if (COUNT && far) { ctr.v[GWN_C_FAR]++; ctr.v[GWN_C_LEAVES]++; }
             }
             acc_leaf += leaf3d<COUNT>(M, nd, cur, qx, qy, qz, me && !far, ncnt, mylist, ctr);
@@ -274,7 +276,7 @@ __device__ double traverse3d_wave(const DevModel &Mdl, double qx, double qy, dou
         }
         if (me) {
             if (COUNT) ctr.v[GWN_C_NODES]++;
-            far = far_term3d<false>(M, nd, cur, qx, qy, qz, acc_far, mask);
+            far = far_term3d<F32>(M, nd, cur, qx, qy, qz, acc_far, mask);
             if (COUNT && far) ctr.v[GWN_C_FAR]++;
         }
         cur = __ballot(me && far) ? uniform_i(nd->escape) : cur + 1;
@@ -290,7 +292,7 @@ template <bool F32, bool COUNT>
 __device__ double traverse3d(const DevModel &Mdl, double qx, double qy, double qz, uint64_t mask, StackLDS &S,
                              int w, int &ncnt, int32_t *__restrict__ mylist, Ctr &ctr)
 {
-    if (!F32 && Mdl.wave_accept) return traverse3d_wave<COUNT>(Mdl, qx, qy, qz, mask, ncnt, mylist, ctr);
+    if (Mdl.wave_accept) return traverse3d_wave<F32, COUNT>(Mdl, qx, qy, qz, mask, ncnt, mylist, ctr);
     const Node3 *__restrict__ nodes = (const Node3 *)Mdl.nodes;
     const TravParams M = trav_params(Mdl);
     const int lane = lane_id();

@@ -164,10 +164,16 @@ def test_config2_full_grid_sampled(oracle):
     check(w[idx], ins[idx], ref)
 
 
-def test_config2_mixed_form(cfg2):
+@pytest.mark.parametrize("wave_accept", [0, 1])
+def test_config2_mixed_form(cfg2, wave_accept):
+    """Mixed form, with per-query far tests and with wave acceptance (in the
+    FP32 pass too): the FP32 error bar, exact classification away from
+    w = 1/2, FP64 values in the re-evaluation band; a call repeats bit for
+    bit."""
     curves, q, ref = cfg2
-    m = G.Model(curves, presets.params(presets.MIXED_2D))
+    m = G.Model(curves, presets.params(presets.MIXED_2D, wave_accept=wave_accept))
     w, ins = run(m, q)
+    assert np.array_equal(run(m, q)[0], w)
     err = np.abs(w - ref)
     assert err.max() < 5e-3, err.max()
     sure = np.abs(ref - 0.5) > BAND
@@ -250,7 +256,7 @@ def test_batch_bitwise_equals_solo(cfg1, cfg2):
     c1, q1, _ = cfg1
     c2, q2, _ = cfg2
     m1 = G.Model(c1, presets.params(presets.FP64_2D, wave_accept=0))
-    m2 = G.Model(c2, presets.params(presets.MIXED_2D))
+    m2 = G.Model(c2, presets.params(presets.MIXED_2D, wave_accept=0))
     s1, _ = run(m1, q1)
     s2, _ = run(m2, q2)
     parts = [(m1, q1[:1000]), (m2, q2[:700]), (m1, q1[1000:1001]), (m2, q2[700:])]
@@ -302,6 +308,24 @@ def test_wave_acceptance(cfg2):
     p.wave_accept = 2
     with pytest.raises(G.GwnError):
         G.gwn_set_params(m.h, p)
+    m.close()
+
+
+@pytest.mark.parametrize("preset", ["FP64_2D", "MIXED_2D"])
+def test_stackless_walk_single_lane(cfg2, preset):
+    """A call of one query runs a wave of one lane, where wave acceptance
+    takes exactly the clusters of the per-query test: the stackless walk
+    (wave_accept = 1) then returns the stack walk's value (wave_accept = 0)
+    bit for bit, in the FP64 form and in both passes of the mixed form."""
+    curves, q, _ = cfg2
+    m = G.Model(curves, presets.params(getattr(presets, preset), wave_accept=0))
+    idx = W.Rng(29, "single-lane").permutation(q.shape[0])[:32]
+    w0 = np.array([run(m, q[i:i + 1])[0][0] for i in idx])
+    far = sum(m.counters(dev(q[i:i + 1]))["far"] for i in idx)
+    m.set(wave_accept=1)
+    w1 = np.array([run(m, q[i:i + 1])[0][0] for i in idx])
+    assert far > 0 and np.all(np.isfinite(w0))
+    assert np.array_equal(w0, w1)
     m.close()
 
 

@@ -156,10 +156,27 @@ def test_config4_fp64_and_mixed(cfg4):
     w, ins = run(m, qs)
     check(w, ins, ref)
     mm = G.Model(P, presets.params(presets.MIXED_3D))
-    wm, insm = run(mm, qs)
-    assert np.abs(wm - ref).max() < 5e-3
     sure = np.abs(ref - 0.5) > BAND
-    assert np.array_equal(insm[sure].astype(bool), (ref >= 0.5)[sure])
+    for wa in (0, 1):   # per-query far tests, then wave acceptance in both passes
+        mm.set(wave_accept=wa)
+        wm, insm = run(mm, qs)
+        assert np.abs(wm - ref).max() < 5e-3
+        assert np.array_equal(insm[sure].astype(bool), (ref >= 0.5)[sure])
+
+
+@pytest.mark.parametrize("preset", ["FP64_3D", "MIXED_3D"])
+def test_stackless_walk_single_lane_3d(cfg4, preset):
+    """A one-query call is a wave of one lane: the stackless walk of wave
+    acceptance gives the stack walk's value bit for bit (far terms, node
+    sets and the near-field list in the same order)."""
+    P, qs, _ = cfg4
+    m = G.Model(P, presets.params(getattr(presets, preset), wave_accept=0))
+    sel = qs[::4]
+    w0 = np.array([run(m, sel[i:i + 1])[0][0] for i in range(sel.shape[0])])
+    m.set(wave_accept=1)
+    w1 = np.array([run(m, sel[i:i + 1])[0][0] for i in range(sel.shape[0])])
+    assert np.all(np.isfinite(w0)) and np.array_equal(w0, w1)
+    m.close()
 
 
 @pytest.mark.parametrize("scale", [1e-6, 1e6])
@@ -182,7 +199,7 @@ def test_scale_invariance_3d(cfg4, scale):
 def test_batch_bitwise_3d(cfg4, sphere):
     P, qs, _ = cfg4
     m1 = G.Model(P, presets.params(presets.FP64_3D, wave_accept=0))
-    m2 = G.Model(sphere, presets.params(presets.MIXED_3D))
+    m2 = G.Model(sphere, presets.params(presets.MIXED_3D, wave_accept=0))
     q2 = W.Rng(46, "b").uniform((100, 3), -1.2, 1.2)
     s1, _ = run(m1, qs)
     s2, _ = run(m2, q2)
