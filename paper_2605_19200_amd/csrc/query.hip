@@ -583,12 +583,15 @@ __device__ __forceinline__ void query2d_body(const LaunchTable &T, const double 
 }
 
 // Launches without mixed segments use k_query2d: without the FP32 pass the
-// kernel fits 96 VGPRs, i.e. five waves per SIMD.  k_query2d_mixed carries
-// both passes; capped at five waves per SIMD it spills 24 bytes per lane
-// and runs about 4 % faster than at the 104 VGPRs (four waves) it takes
-// uncapped.
+// kernel fits 96 VGPRs with a 44-byte spill (five waves per SIMD); capped
+// at 80 VGPRs (six waves) it spills 104 bytes per lane but hides more of
+// the dependent node loads: 3 % faster on the 1024^2 drawing than at five
+// waves, as fast as at seven (148 bytes of spill), and eight are 3 %
+// slower.  k_query2d_mixed carries both passes; capped at six waves per
+// SIMD it runs 3 % faster than at five and 7 % faster than at the 104
+// VGPRs (four waves) it takes uncapped.
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_query2d(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_query2d(
     LaunchTable T, const double *__restrict__ pts, const int32_t *__restrict__ perm, double *__restrict__ out_w,
     uint8_t *__restrict__ out_in, long long *counters)
 {
@@ -597,7 +600,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_query2d_mixed(LaunchTable T, const double *__restrict__ pts,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_query2d_mixed(LaunchTable T, const double *__restrict__ pts,
                                                           const int32_t *__restrict__ perm,
                                                           double *__restrict__ out_w, uint8_t *__restrict__ out_in,
                                                           long long *counters)
