@@ -39,6 +39,6 @@ def max_error(ps: np.ndarray) -> float:
 
 if __name__ == "__main__":
     ps = coefficients()
-    print("constexpr double kAtanP[%d] = {" % len(ps))
+    print("__constant__ double kAtanP[%d] = {" % len(ps))
     print(",\n".join("    %.17g" % c for c in ps) + "};")
     print("// max |r P(r^2) - atan(r)| = %.3g" % max_error(ps))

@@ -110,13 +110,17 @@ __device__ __forceinline__ float fast_rcp(float d) { return __builtin_amdgcn_rcp
 // atan2(y, x) for finite (x, y) != (0, 0), absolute error ~1e-15.
 // Octant reduction to t = min/max in [0, 1], then (t - 1) / (t + 1) above
 // tan(pi/8), so the polynomial runs on |r| <= tan(pi/8); one division by a
-// refined hardware reciprocal.  Coefficients: atan_coeffs.py.
+// refined hardware reciprocal.  Coefficients: atan_coeffs.py.  They live in
+// constant memory and arrive by scalar loads: as literals the compiler
+// hoisted them out of the traversal loop into 16 vector registers and
+// spilled them.
+__constant__ double kAtanP[10] = {
+    0.99999999999999933,  -0.33333333333221649, 0.19999999978414348,  -0.1428571266185861,
+    0.11111048822077878,  -0.090895287796835464, 0.076735172520470213, -0.065058395774881372,
+    0.05024193570775376,  -0.025307491891893075};
+
 __device__ __forceinline__ double fast_atan2(double y, double x)
 {
-    constexpr double kAtanP[10] = {
-        0.99999999999999933,  -0.33333333333221649, 0.19999999978414348,  -0.1428571266185861,
-        0.11111048822077878,  -0.090895287796835464, 0.076735172520470213, -0.065058395774881372,
-        0.05024193570775376,  -0.025307491891893075};
     const double ax = fabs(x), ay = fabs(y);
     const double mn = fmin(ax, ay), mx = fmax(ax, ay);
     const bool big = mn > 0.41421356237309503 * mx;
@@ -583,15 +587,15 @@ __device__ __forceinline__ void query2d_body(const LaunchTable &T, const double 
 }
 
 // Launches without mixed segments use k_query2d: without the FP32 pass the
-// kernel fits 96 VGPRs with a 44-byte spill (five waves per SIMD); capped
-// at 80 VGPRs (six waves) it spills 104 bytes per lane but hides more of
-// the dependent node loads: 3 % faster on the 1024^2 drawing than at five
-// waves, as fast as at seven (148 bytes of spill), and eight are 3 %
-// slower.  k_query2d_mixed carries both passes; capped at six waves per
-// SIMD it runs 3 % faster than at five and 7 % faster than at the 104
-// VGPRs (four waves) it takes uncapped.
+// kernel fits 93 VGPRs with no spill (five waves per SIMD); capped at 72
+// VGPRs (seven waves) it spills 84 bytes per lane, outside the hot paths,
+// and hides more of the dependent node loads: 5 % faster on the 1024^2
+// drawing than at five waves and 3 % faster than at six.
+// k_query2d_mixed carries both passes; capped at six waves per SIMD (80
+// VGPRs, 72 bytes of spill) it runs 3 % faster than at five or seven and
+// 7 % faster than at the 104 VGPRs (four waves) it takes uncapped.
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_query2d(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_query2d(
     LaunchTable T, const double *__restrict__ pts, const int32_t *__restrict__ perm, double *__restrict__ out_w,
     uint8_t *__restrict__ out_in, long long *counters)
 {
