@@ -97,6 +97,10 @@ __device__ double leaf3d(const TravParams &M, const Node3 *__restrict__ nd, int 
         if (r2 >= kLeafRuleRatio[2] * kLeafRuleRatio[2]) { off = c0 + c1; cnt = c2; }
         else if (r2 >= kLeafRuleRatio[1] * kLeafRuleRatio[1]) { off = c0; cnt = c1; }
         const QNode3 *__restrict__ qn = (const QNode3 *)M.qnodes + nd->aux + off;
+        // four nodes' scalar loads in flight before the first is used (the
+        // sum keeps its order): traversal 149 -> 113 ms on the CAD
+        // assembly, 36.0 -> 34.5 ms on the bodies grid (eight: no better)
+#pragma unroll 4
         for (int k = 0; k < cnt; ++k) {
             const double rx = qn[k].x[0] - qx, ry = qn[k].x[1] - qy, rz = qn[k].x[2] - qz;
             const double rr = rx * rx + ry * ry + rz * rz;
