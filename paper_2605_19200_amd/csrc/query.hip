@@ -588,8 +588,9 @@ __device__ __forceinline__ void query2d_body(const LaunchTable &T, const double 
 
 // Launches without mixed segments use k_query2d: without the FP32 pass the
 // kernel fits 93 VGPRs with no spill (five waves per SIMD); capped at 72
-// VGPRs (seven waves) it spills 84 bytes per lane, outside the hot paths,
-// and hides more of the dependent node loads: 5 % faster on the 1024^2
+// VGPRs (seven waves) it spills 84 bytes per lane, around the leaf
+// bisection (entered by a small share of leaf visits), and hides more of
+// the dependent node loads: 5 % faster on the 1024^2
 // drawing than at five waves and 3 % faster than at six.
 // k_query2d_mixed carries both passes; capped at six waves per SIMD (80
 // VGPRs, 72 bytes of spill) it runs 3 % faster than at five or seven and
