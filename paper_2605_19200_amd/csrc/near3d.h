@@ -65,22 +65,6 @@ struct QuadTables {
     double xr[kGKr], wr[kGKr], gr[kRadialN];
 };
 
-// Error estimate of a Kronrod / Gauss pair (the truncation part): resasc =
-// the Kronrod integral of |f - K / len| times the panel length.  The
-// difference |K - G| measures the Gauss rule's error; for an integrand in
-// the asymptotic regime the Kronrod rule's error is about resasc times
-// (|K - G| / resasc)^((3n + 2) / (2n)), with an exponent of 1.6 to 1.7 for
-// n = 4..7.  The estimate takes the power 1.5, as QUADPACK does, but
-// without its extra factor 200 inside the power, which on these sinh-graded
-// radial pieces over-estimated errors of ~1e-11 as ~1e-6.
-GWN_HD inline double gk_error(double K, double G, double resasc)
-{
-    const double e = fabs(K - G);
-    if (resasc == 0.0 || e == 0.0) return e;
-    const double r = fmin(1.0, e / resasc);
-    return resasc * r * sqrt(r);
-}
-
 // Rounding level of a Kronrod sum (QUADPACK's floor, 50 eps times the sum of
 // |f|): an estimate below it cannot be improved by refinement.  The radial
 // rule passes the sum of |f| times each node's noise factor: A = H - q W
@@ -191,6 +175,25 @@ GWN_HD inline double inv_fast(double x)
 #else
     return 1.0 / x;
 #endif
+}
+
+// Error estimate of a Kronrod / Gauss pair (the truncation part): resasc =
+// the Kronrod integral of |f - K / len| times the panel length.  The
+// difference |K - G| measures the Gauss rule's error; for an integrand in
+// the asymptotic regime the Kronrod rule's error is about resasc times
+// (|K - G| / resasc)^((3n + 2) / (2n)), with an exponent of 1.6 to 1.7 for
+// n = 4..7.  The estimate takes the power 1.5, as QUADPACK does, but
+// without its extra factor 200 inside the power, which on these sinh-graded
+// radial pieces over-estimated errors of ~1e-11 as ~1e-6.
+// It runs once per radial part, so the quotient and the square root use
+// the refined hardware estimates (inv_fast, inv_sqrt) rather than the IEEE
+// sequences.
+GWN_HD inline double gk_error(double K, double G, double resasc)
+{
+    const double e = fabs(K - G);
+    if (resasc == 0.0 || e == 0.0) return e;
+    const double r = fmin(1.0, e * inv_fast(resasc));
+    return resasc * r * (r * inv_sqrt(r));
 }
 
 // solid angle density det[A, A_u, A_v] / |A|^3, and 1 / |A| in *rs (0 when
@@ -461,20 +464,24 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
     const double lx = fr.Su[0] * ru + fr.Sv[0] * rv, ly = fr.Su[1] * ru + fr.Sv[1] * rv,
                  lz = fr.Su[2] * ru + fr.Sv[2] * rv;
     const double L = sqrt(lx * lx + ly * ly + lz * lz);
-    const double eps = L > 0.0 ? fr.dist / L : 1.0;
+    // quotients by refined hardware reciprocals (one per lane and outer
+    // node; the IEEE division sequences cost 3 % of the launch)
+    const double eps = L > 0.0 ? fr.dist * inv_fast(L) : 1.0;
     const bool uni = eps >= 0.5;
     double mu = 1.0, cuts[4] = {0.0, 0.5, 1.0, 1.0};
     int np = 2;
     if (!uni) {
-        mu = asinh(1.0 / eps);
-        const double s4 = asinh(4.0) / mu, s01 = asinh(0.1 / eps) / mu;
+        const double ieps = L * inv_fast(fr.dist);
+        mu = asinh(ieps);
+        const double imu = inv_fast(mu);
+        const double s4 = asinh(4.0) * imu, s01 = asinh(0.1 * ieps) * imu;
         np = 1;
         cuts[1] = 1.0;
         cuts[2] = 1.0;
         if (s01 > s4) { cuts[1] = s4; cuts[2] = s01; np = 3; }
         else if (s4 < 1.0) { cuts[1] = s4; np = 2; }
     }
-    const double tol_piece = tol_f / fabs(cr) / np;
+    const double tol_piece = cr != 0.0 ? tol_f * inv_fast(fabs(cr) * np) : INFINITY;
     const double a = cuts[p], b = cuts[p + 1];
     double tval = 0.0, te = 0.0, trnd = 0.0;
     bool tovf = false;
@@ -503,7 +510,7 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
             const double tru = wv.shfl(ru, task), trv = wv.shfl(rv, task);
             const double teps = wv.shfl(eps, task), tmu = wv.shfl(mu, task);
             const int tuni = wv.shfl((int)uni, task);
-            const double w = (tb - ta) / nsub;
+            const double w = (tb - ta) * ldexp(1.0, -l);   // / nsub, exactly
             const double xa = ta + (ra & (nsub - 1)) * w;
             const bool node = vra && i < kGKr;
             double fx = 0.0, nz = 0.0;
