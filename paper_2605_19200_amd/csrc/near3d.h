@@ -501,11 +501,13 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
             te = 0.0;
             trnd = 0.0;
         }
+        // lane k: the lane of the k-th pending task, found once per level
+        const int kpos = ln < __builtin_popcountll(pend) ? kth_bit(pend, ln) : 0;
 #pragma unroll 1
         for (int r0 = 0; r0 < nra; r0 += 4) {
             const int ra = r0 + g;
             const bool vra = ra < nra;
-            const int task = vra ? kth_bit(pend, ra >> l) : 0;
+            const int task = wv.shfl(kpos, vra ? ra >> l : 0);
             const double ta = wv.shfl(a, task), tb = wv.shfl(b, task);
             const double tru = wv.shfl(ru, task), trv = wv.shfl(rv, task);
             const double teps = wv.shfl(eps, task), tmu = wv.shfl(mu, task);
