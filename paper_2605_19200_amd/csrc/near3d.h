@@ -503,6 +503,9 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
         }
         // lane k: the lane of the k-th pending task, found once per level
         const int kpos = ln < __builtin_popcountll(pend) ? kth_bit(pend, ln) : 0;
+        // this lane's rank among the pending tasks (if it holds one)
+        const bool own = (pend >> ln) & 1;
+        const int rank = __builtin_popcountll(pend & ((1ull << ln) - 1));
 #pragma unroll 1
         for (int r0 = 0; r0 < nra; r0 += 4) {
             const int ra = r0 + g;
@@ -541,14 +544,28 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
             const double asc = sum16(wv, wk * fabs(fx - K));
             const double noise = sum16(wv, wk * nz);
             const double pval = w * K, perr = gk_error(w * K, w * G, w * asc), prnd = gk_round(w * noise);
-#pragma unroll 1
-            for (int gg = 0; gg < 4 && r0 + gg < nra; ++gg) {
-                const int tk = wv.bcast(task, 16 * gg);
-                const double v1 = wv.bcast(pval, 16 * gg), e1 = wv.bcast(perr, 16 * gg), r1 = wv.bcast(prnd, 16 * gg);
-                if (ln == tk) {
+            if (l == 0) {
+                // one part per task: the task of rank r0 + g takes group g's
+                // sums, all four groups at once
+                const int kk = rank - r0;
+                const bool mine = own && kk >= 0 && kk < 4;
+                const int src = 16 * (mine ? kk : 0);
+                const double v1 = wv.shfl(pval, src), e1 = wv.shfl(perr, src), r1 = wv.shfl(prnd, src);
+                if (mine) {
                     tval += v1;
                     te += e1;
                     trnd += r1;
+                }
+            } else {
+#pragma unroll 1
+                for (int gg = 0; gg < 4 && r0 + gg < nra; ++gg) {
+                    const int tk = wv.bcast(task, 16 * gg);
+                    const double v1 = wv.bcast(pval, 16 * gg), e1 = wv.bcast(perr, 16 * gg), r1 = wv.bcast(prnd, 16 * gg);
+                    if (ln == tk) {
+                        tval += v1;
+                        te += e1;
+                        trnd += r1;
+                    }
                 }
             }
         }
