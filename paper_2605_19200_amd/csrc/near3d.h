@@ -45,13 +45,16 @@
 
 namespace gwn {
 
-// Gauss points of the outer (G4 / K9) and radial (G6 / K13) pairs: on the
-// CAD assembly's near-field pairs the cheapest that met the tolerance
-// without refinement in most leaves (about 1.3x the integrand evaluations
-// of the fixed 8 x 12-point rule it replaced; pairs (5, 5) to (7, 7) took
-// 1.4x to 2.4x)
+// Gauss points of the outer (G4 / K9) and radial (G7 / K15) pairs.  The
+// outer pair is the cheapest that met the tolerance without refinement in
+// most leaves of the CAD assembly's near-field pairs.  A radial part is one
+// 16-lane group's task whatever its node count, so the 15-node rule costs
+// no more per part than the 13-node one and, of higher degree, needs fewer
+// refined parts: near field 53.1 -> 51.8 ms on the bodies grid, 826 -> 783
+// ms on the CAD assembly, and 2 instead of 5 of its queries overrun the
+// refinement budget.
 constexpr int kOuterN = 4;
-constexpr int kRadialN = 6;
+constexpr int kRadialN = 7;
 constexpr int kGKo = 2 * kOuterN + 1;      // Kronrod nodes per outer panel
 constexpr int kGKr = 2 * kRadialN + 1;     // Kronrod nodes per radial piece
 constexpr int kMaxPanelsSide = 40;
@@ -440,9 +443,9 @@ constexpr int kSubPerChunk = 2;
 // H comes in up to three pieces (tau <= 4 eps, 4 eps <= tau <= 0.1, tau >=
 // 0.1 with eps = d / |J (p - c)|; two uniform pieces when eps >= 0.5; no
 // piece reaches past tau = 1), each the task of lane 3 m + p: integrated
-// by the 13-point Kronrod rule on 1, 2, 4, ... 2^kRadialLevels equal parts
+// by the 15-point Kronrod rule on 1, 2, 4, ... 2^kRadialLevels equal parts
 // until its estimate meets its share.  The parts of the pending tasks are
-// shared out over the wave's four groups of 16 lanes, one part (13 nodes)
+// shared out over the wave's four groups of 16 lanes, one part (15 nodes)
 // per group and round; each task adds the sums of its parts in their order.
 template <class Wv, class CtrT>
 GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double *__restrict__ h, const Curve2 &cv,
