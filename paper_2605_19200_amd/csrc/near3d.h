@@ -441,7 +441,7 @@ constexpr int kSubPerChunk = 2;
 // integral_0^1 g(c + tau (p - c)) tau dtau is sinh-graded at tau = 0 and
 // taken to the tolerance tol_f / |cross|.
 // H comes in up to three pieces (tau <= 4 eps, 4 eps <= tau <= 0.1, tau >=
-// 0.1 with eps = d / |J (p - c)|; two uniform pieces when eps >= 0.5; no
+// 0.1 with eps = d / |J (p - c)|; one uniform piece when eps >= 0.5; no
 // piece reaches past tau = 1), each the task of lane 3 m + p: integrated
 // by the 15-point Kronrod rule on 1, 2, 4, ... 2^kRadialLevels equal parts
 // until its estimate meets its share.  The parts of the pending tasks are
@@ -475,8 +475,11 @@ GWN_HD inline void outer_values(const Wv &wv, const QuadTables &Q, const double 
     // node; the IEEE division sequences cost 3 % of the launch)
     const double eps = L > 0.0 ? fr.dist * inv_fast(L) : 1.0;
     const bool uni = eps >= 0.5;
-    double mu = 1.0, cuts[4] = {0.0, 0.5, 1.0, 1.0};
-    int np = 2;
+    // eps >= 0.5: the integrand is smooth on [0, 1] and one piece is
+    // enough (refined if its estimate says otherwise); two fixed halves cost
+    // 34 % more integrand evaluations and 11 % more time on the bodies grid
+    double mu = 1.0, cuts[4] = {0.0, 1.0, 1.0, 1.0};
+    int np = 1;
     if (!uni) {
         const double ieps = L * inv_fast(fr.dist);
         mu = asinh(ieps);
